@@ -1,0 +1,146 @@
+"""Seeded synthetic inputs for Kuramoto-Sivashinsky connecting-curve problems.
+
+This module only draws random numbers and lays them out; it holds none of the
+method's arithmetic (no residual, cost, adjoint or step).  Both the FP64 CPU
+oracle and the GPU library consume what it returns, so the two sides always
+see the same numbers.
+
+State layout shared by both sides: one complex array per curve of shape
+``[n_s, n_modes]`` holding the Fourier coefficients of every s-row (row 0 is
+the endpoint at s = -inf, row n_s-1 the endpoint at s = +inf).  ``n_modes``
+is supplied by the caller; mode 0 is real.
+
+Smooth random state (the recipe of every workload):
+    u(x) = amp * sum_{k=1..kmax} (a_k cos(2 pi k x / L) + b_k sin(2 pi k x / L)) / k^2
+with a_k, b_k ~ N(0, 1), i.e. coefficient u_hat_k = amp * (a_k - i b_k) / (2 k^2)
+and u_hat_0 = 0.  Draw order per curve: a(B), b(B), [a(A), b(A)], a(p), b(p),
+from ``numpy.random.default_rng(SeedSequence([config, curve]))``.
+
+Initial curve: u_j = (1 - sigma_j) A + sigma_j B + sin(pi sigma_j) p with
+sigma_j = j / (n_s - 1).
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass, field
+
+import numpy as np
+
+__all__ = [
+    "CurveSpec",
+    "smooth_coeffs",
+    "blend_curve",
+    "config_specs",
+    "make_curve",
+    "round_to",
+    "random_direction",
+]
+
+
+@dataclass(frozen=True)
+class CurveSpec:
+    """Shape and seeds of one synthetic curve."""
+
+    n_s: int
+    n_x: int
+    L: float
+    kmax_end: int          # highest mode of the random endpoint(s)
+    amp_end: float
+    kmax_pert: int         # highest mode of the sin(pi sigma) perturbation
+    amp_pert: float
+    random_A: bool         # False: A = 0 (the trivial equilibrium)
+    seed: tuple = field(default=(0, 0))
+    map: str = "rational"  # "rational" (s = s0 + S cot(theta)) or "finite" (s = T sigma)
+    scale: float = 40.0    # S for the rational map, T for the finite map
+    s0: float = 0.0
+
+
+def smooth_coeffs(rng: np.random.Generator, kmax: int, amp: float, n_modes: int) -> np.ndarray:
+    """Coefficients u_hat_k = amp (a_k - i b_k) / (2 k^2), k = 1..kmax; zero elsewhere."""
+    a = rng.standard_normal(kmax)
+    b = rng.standard_normal(kmax)
+    out = np.zeros(n_modes, dtype=np.complex128)
+    k = np.arange(1, kmax + 1)
+    kk = min(kmax, n_modes - 1)
+    out[1:kk + 1] = (amp * (a - 1j * b) / (2.0 * k.astype(np.float64) ** 2))[:kk]
+    return out
+
+
+def blend_curve(A: np.ndarray, B: np.ndarray, p: np.ndarray, n_s: int) -> np.ndarray:
+    """u_j = (1 - sigma_j) A + sigma_j B + sin(pi sigma_j) p, sigma_j = j / (n_s - 1)."""
+    sig = np.arange(n_s, dtype=np.float64) / (n_s - 1)
+    U = (1.0 - sig)[:, None] * A[None, :] + sig[:, None] * B[None, :] \
+        + np.sin(np.pi * sig)[:, None] * p[None, :]
+    U[0] = A
+    U[-1] = B
+    return U
+
+
+def make_curve(spec: CurveSpec, n_modes: int):
+    """Return (A_hat, B_hat, U_hat[n_s, n_modes]) for one seeded curve."""
+    rng = np.random.default_rng(np.random.SeedSequence(list(spec.seed)))
+    B = smooth_coeffs(rng, spec.kmax_end, spec.amp_end, n_modes)
+    if spec.random_A:
+        A = smooth_coeffs(rng, spec.kmax_end, spec.amp_end, n_modes)
+    else:
+        A = np.zeros(n_modes, dtype=np.complex128)
+    p = smooth_coeffs(rng, spec.kmax_pert, spec.amp_pert, n_modes)
+    return A, B, blend_curve(A, B, p, spec.n_s)
+
+
+def config_specs(cfg: int, n_curves: int | None = None) -> list[CurveSpec]:
+    """The synthetic workloads.
+
+    0: one curve, L=22, N_x=32, N_s=64, A=0, B=smooth(4,1), p=smooth(4,0.1), FP64.
+    1: one curve, L=39, N_x=64, N_s=512, modes <= 6, perturbation 0.2, FP32.
+    2: one curve, L=100, N_x=256, N_s=8192, random A and B with modes <= 12,
+       perturbation 0.3, FP32.
+    3: 256 curves of uneven shape, N_x in {32,64,128}, N_s in [128, 2048],
+       L in {22,39,66}, each seeded as workload 0.
+    4: 64 curves, L=66, N_x=128, N_s=1024, finite map T=20 (endpoints come
+       from a stored trajectory file; this spec gives the shape only).
+    """
+    if cfg == 0:
+        return [CurveSpec(64, 32, 22.0, 4, 1.0, 4, 0.1, False, (0, 0))]
+    if cfg == 1:
+        return [CurveSpec(512, 64, 39.0, 6, 1.0, 6, 0.2, False, (1, 0))]
+    if cfg == 2:
+        return [CurveSpec(8192, 256, 100.0, 12, 1.0, 12, 0.3, True, (2, 0))]
+    if cfg == 3:
+        n = 256 if n_curves is None else n_curves
+        srng = np.random.default_rng(np.random.SeedSequence([3, 10**6]))
+        nxs = srng.choice([32, 64, 128], size=n)
+        nss = srng.integers(128, 2048, size=n, endpoint=True)
+        Ls = srng.choice([22.0, 39.0, 66.0], size=n)
+        return [CurveSpec(int(nss[c]), int(nxs[c]), float(Ls[c]), 4, 1.0, 4, 0.1, False, (3, c))
+                for c in range(n)]
+    if cfg == 4:
+        n = 64 if n_curves is None else n_curves
+        return [CurveSpec(1024, 128, 66.0, 6, 1.0, 4, 0.1, True, (4, c), "finite", 20.0)
+                for c in range(n)]
+    raise ValueError(f"unknown workload {cfg}")
+
+
+def round_to(U: np.ndarray, dtype) -> np.ndarray:
+    """Round complex128 data to the run precision (complex64 for FP32) and back."""
+    if np.dtype(dtype) == np.float32:
+        return U.astype(np.complex64).astype(np.complex128)
+    return U.astype(np.complex128)
+
+
+def random_direction(seed, n_s: int, n_modes: int, kmax: int = 8) -> np.ndarray:
+    """Smooth seeded direction: sin(pi sigma) in s times random modes k <= kmax."""
+    rng = np.random.default_rng(np.random.SeedSequence(list(seed)))
+    sig = np.arange(n_s, dtype=np.float64) / (n_s - 1)
+    v = np.zeros((n_s, n_modes), dtype=np.complex128)
+    kk = min(kmax, n_modes - 1)
+    coef = rng.standard_normal(kk + 1) + 1j * rng.standard_normal(kk + 1)
+    coef[0] = coef[0].real
+    amp = np.sin(np.pi * sig)
+    # a second, faster s-profile so the direction is not rank one
+    amp2 = np.sin(2 * np.pi * sig)
+    coef2 = rng.standard_normal(kk + 1) + 1j * rng.standard_normal(kk + 1)
+    coef2[0] = coef2[0].real
+    v[:, :kk + 1] = amp[:, None] * coef[None, :] + 0.5 * amp2[:, None] * coef2[None, :]
+    v[0] = 0
+    v[-1] = 0
+    return v
