@@ -1,0 +1,204 @@
+"""Benchmark: fused J + gradient evaluations of a batch of KS connecting curves
+on one MI355X.
+
+A step is one evaluation of J^2 and its adjoint gradient for every curve of
+the batch (the fused tile kernel plus the FP64 per-curve finalization).
+Workload (default): 64 curves, L = 66, N_x = 128 (43 kept modes), N_s = 1024,
+finite map T = 20, FP32 with FP64 cost reduction; endpoints are stored
+KS-trajectory states, the interior is the blend plus a seeded perturbation.
+
+Prints one JSON line.  value = curve-point evals/s = sum_c (N_s - 2) * steps / s.
+Also reported: the plain policy (one launch per curve), the streaming
+roofline (the batch replicated past the caches), and the FP64 oracle timed on
+the host on a bounded sample.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "curve-point gradient evals/s (J+∇J) & % HBM roofline, batched vs plain"
+HBM_PEAK_GBS = 8000.0
+
+
+def _specs_and_states(workload: str):
+    import ksinputs
+    if workload == "c4":
+        specs, Us = ksinputs.config4_curves(64)
+        return specs, Us, "finite"
+    cfg = {"c1": 1, "c2": 2, "c3": 3}[workload]
+    specs = ksinputs.config_specs(cfg)
+    Us = []
+    for s in specs:
+        K1 = (s.n_x - 1) // 3 + 1
+        Us.append(ksinputs.make_curve(s, K1)[2])
+    return specs, Us, specs[0].map
+
+
+def _describe(workload, specs):
+    ns = [s.n_s for s in specs]
+    nx = sorted(set(s.n_x for s in specs))
+    return {
+        "workload": {
+            "c4": "64 KS curves, L=66, N_x=128, N_s=1024, finite map T=20 (batched autograd-path shape)",
+            "c1": "1 KS curve, L=39, N_x=64, N_s=512",
+            "c2": "1 KS curve, L=100, N_x=256, N_s=8192",
+            "c3": "256 uneven KS curves, N_x in {32,64,128}, N_s in [128,2048]",
+        }[workload],
+        "curves": len(specs),
+        "n_x": nx if len(nx) > 1 else nx[0],
+        "n_s_total": int(sum(ns)),
+        "curve_points": int(sum(n - 2 for n in ns)),
+        "state_MB": round(sum(n * ((s.n_x - 1) // 3 + 1) * 8 for n, s in zip(ns, specs)) / 1e6, 3),
+    }
+
+
+def _time(torch, fn, steps, stream):
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    for _ in range(steps):
+        fn()
+    e1.record(stream)
+    e1.synchronize()
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / steps  # ms
+
+
+def cpu_baseline(specs, Us, budget_s=12.0):
+    """The FP64 oracle (as it stands) on the host: J2 + gradient per curve,
+    curves taken in order until the time budget is used."""
+    import oracle
+    import ksinputs
+    t0 = time.perf_counter()
+    pts = 0
+    n = 0
+    while True:
+        s, U = specs[n % len(specs)], Us[n % len(Us)]
+        c = oracle.Curve(s.n_s, s.n_x, s.L, s.map, s.scale, s.s0)
+        Ur = ksinputs.round_to(U, np.float32)
+        oracle.J2(c, Ur)
+        oracle.grad(c, Ur)
+        pts += s.n_s - 2
+        n += 1
+        el = time.perf_counter() - t0
+        if el >= budget_s:
+            break
+    return {
+        "value": pts / el, "unit": "curve-point evals/s", "cores": 1, "kind": "oracle",
+        "sample": f"{n} curve evaluations (J2 + gradient, FP64 NumPy, single thread) in {el:.1f} s",
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--workload", default="c4", choices=["c4", "c1", "c2", "c3"])
+    ap.add_argument("--no-cpu", action="store_true", help="skip the host oracle baseline")
+    ap.add_argument("--no-extras", action="store_true", help="skip plain and streaming legs")
+    ap.add_argument("--replicas", type=int, default=48, help="streaming-leg replication factor")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the batched path "
+              "is single-device by design", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_2301_11704_amd as ksc
+
+    torch.cuda.set_device(0)
+    stream = torch.cuda.current_stream()
+    specs, Us, _ = _specs_and_states(args.workload)
+    descs = [ksc.CurveDesc(s.n_s, s.n_x, s.L, s.map, s.scale, s.s0) for s in specs]
+    prob = ksc.Problem(descs, dtype=torch.float32)
+    X = prob.new_state()
+    for c, U in enumerate(Us):
+        prob.upload(X, c, U)
+    G = torch.empty_like(X)
+    J2 = torch.empty(len(specs), dtype=torch.float64, device="cuda")
+    prob.tune(None)
+    policy, waves = prob.launch
+
+    def step():
+        prob.eval_grad(X, G)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    ms = _time(torch, step, args.steps, stream)
+    # the dominant kernel alone (no per-curve finalization)
+    ms_kernel = _time(torch, lambda: prob.eval_grad(X, G, want_J2=False), args.steps, stream)
+
+    info = _describe(args.workload, specs)
+    pts = info["curve_points"]
+    value = pts / (ms * 1e-3)
+    km_rows = sum(s.n_s * ((s.n_x - 1) // 3 + 1) for s in specs)
+    alg_bytes = 16.0 * km_rows  # read + write 8 B per kept mode per row (FP32)
+    achieved = alg_bytes / (ms_kernel * 1e-3) / 1e9
+
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "curve-point evals/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": dict(info, launch={"policy": policy, "waves_per_tile": waves}),
+        "roofline": {
+            "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+            "kernel": "fused J+grad tile kernel", "kernel_ms": ms_kernel,
+            "alg_bytes_per_launch": alg_bytes,
+        },
+    }
+
+    if not args.no_extras:
+        prob.set_launch(ksc.KSC_LAUNCH_PLAIN, waves)
+        ms_plain = _time(torch, step, max(10, args.steps // 4), stream)
+        prob.set_launch(policy, waves)
+        out["plain"] = {"value": pts / (ms_plain * 1e-3), "ms_per_step": ms_plain,
+                        "speedup_batched_vs_plain": ms_plain / ms}
+        if args.workload == "c4" and args.replicas > 1:
+            big = [d for _ in range(args.replicas) for d in descs]
+            pb = ksc.Problem(big, dtype=torch.float32)
+            Xb = X.repeat(args.replicas)
+            Gb = torch.empty_like(Xb)
+            pb.set_launch(policy, waves)
+            for _ in range(3):
+                pb.eval_grad(Xb, Gb, want_J2=False)
+            msb = _time(torch, lambda: pb.eval_grad(Xb, Gb, want_J2=False),
+                        max(5, args.steps // 10), stream)
+            bb = alg_bytes * args.replicas
+            out["streaming"] = {
+                "replicas": args.replicas, "state_GB": Xb.numel() * 4 / 1e9, "kernel_ms": msb,
+                "achieved_GBs": bb / (msb * 1e-3) / 1e9,
+                "frac_hbm": bb / (msb * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                "curve_points_per_s": pts * args.replicas / (msb * 1e-3),
+            }
+            del Xb, Gb, pb
+
+    if not args.no_cpu:
+        out["cpu_baseline"] = cpu_baseline(specs, Us)
+        out["cpu_baseline"]["gpu_over_cpu"] = value / out["cpu_baseline"]["value"]
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

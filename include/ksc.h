@@ -1,0 +1,183 @@
+/*
+ * ksc.h -- C ABI of the MI355X library that evaluates the cost J^2 of a
+ * discretized Kuramoto-Sivashinsky connecting curve, its adjoint gradient, and
+ * takes adjoint-descent steps that deform the curve toward a connecting orbit
+ * (O. Ashtari & T. M. Schneider, "Jacobian-Free Variational Method for
+ * Constructing Connecting Orbits in Nonlinear Dynamical Systems",
+ * arXiv:2301.11704).
+ *
+ * Discrete problem (one curve; every call works on a batch of curves):
+ *   state        u_hat[j][k], j = 0..n_s-1 rows along the curve, k = 0..K the
+ *                kept Fourier modes of the periodic field u(x) on [0, L),
+ *                K = (n_x - 1) / 3 (2/3-rule dealiasing).  Row 0 is the endpoint
+ *                at s = -inf, row n_s-1 the endpoint at s = +inf (the curve's
+ *                asymptotic conditions, Sec. II, eq. connecting_orbit_def).
+ *                Mode 0 is real; its imaginary part is ignored on input and
+ *                written as 0.
+ *   layout       curve-major, row-major, interleaved (re, im) scalars of the
+ *                problem's dtype: curve c starts at ksc_state_offset(p, c)
+ *                scalars, row j of it 2*(K+1)*j scalars later.
+ *   s-grid       sigma_j = j / (n_s - 1); rational map s = s0 + S cot(theta),
+ *                theta = pi (1 - sigma) (Sec. IV, eq. Rational_domain), or the
+ *                finite map s = T sigma.  d/ds = g_j (.)_{j+1} - (.)_{j-1} over
+ *                2 dsigma with g = d sigma / d s.
+ *   residual     r = -u_s - u u_x - u_xx - u_xxxx (Sec. V.A, eq. KSE_residual)
+ *                on interior rows, r = 0 on the two end rows (Sec. V.C.1).
+ *   cost         J2 = int int r^2 dx ds (Sec. II, eq. cost_function_general):
+ *                trapezoid in sigma with weights dsigma / g_j, Parseval in x.
+ *   adjoint      L^dagger(u; r) = r_s + u r_x - r_xx - r_xxxx (Sec. V.A and
+ *                Appendix A); this is the exact adjoint of the discrete
+ *                directional derivative, so the Euclidean gradient of J2 is
+ *                dJ2/d(Re,Im) u_hat[j][k] = 2 w_j L c_k L^dagger[j][k]
+ *                (w_j = dsigma / g_j, c_0 = 1, c_k = 2 otherwise), zero on the
+ *                end rows and for Im of mode 0.
+ *   step         semi-implicit forward Euler of du/dtau = -L^dagger(u; r)
+ *                (eq. KSE_G, Sec. V.C.3): the stiff Fourier-diagonal part is
+ *                implicit, u_hat <- u_hat - dtau L^dagger / (1 + dtau A_k^2),
+ *                A_k = q_k^2 - q_k^4, q_k = 2 pi k / L.
+ *   J_arc        int |r| |u_s| ds / int |u_s| ds (eq. J_arc).
+ *
+ * Conventions for every call:
+ *   - All data pointers are DEVICE pointers owned by the caller, except
+ *     ksc_query_flags' output and the descriptor array of ksc_create, which
+ *     are host pointers.  The library owns only the workspace it allocates in
+ *     ksc_create and frees in ksc_destroy.
+ *   - Work is enqueued asynchronously on the problem's HIP stream; nothing
+ *     blocks the host except ksc_create, ksc_destroy, ksc_tune and
+ *     ksc_query_flags.
+ *   - Every call returns a ksc_status; on failure nothing was enqueued and
+ *     ksc_last_error() returns a message (thread-local).  Argument, shape and
+ *     support errors are detected on the host before any launch.
+ *   - Supported: n_x in {8, 16, 32, 64, 128, 256}, n_s >= 3, L > 0,
+ *     scale > 0.  dtype KSC_F32 computes in FP32 and accumulates J2 in FP64;
+ *     KSC_F64 computes in FP64.
+ *   - Kernels are deterministic: the same inputs give bitwise-equal outputs.
+ */
+#ifndef KSC_H
+#define KSC_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  KSC_OK = 0,
+  KSC_ERR_ARG = -1,         /* null pointer, bad enum or out-of-range value */
+  KSC_ERR_SHAPE = -2,       /* n_s < 3, curve index out of range, ... */
+  KSC_ERR_UNSUPPORTED = -3, /* n_x not a supported power of two */
+  KSC_ERR_HIP = -4,         /* a HIP runtime call failed */
+  KSC_ERR_NONFINITE = -5,   /* reported through ksc_query_flags */
+  KSC_ERR_DIVERGED = -6,    /* reported through ksc_query_flags */
+  KSC_ERR_STATE = -7        /* call not valid in the problem's current state */
+} ksc_status;
+
+typedef enum { KSC_F32 = 0, KSC_F64 = 1 } ksc_dtype;
+
+typedef enum {
+  KSC_MAP_RATIONAL = 0, /* s = s0 + scale * cot(pi (1 - sigma)); scale is the paper's S */
+  KSC_MAP_FINITE = 1    /* s = scale * sigma; scale is the length T */
+} ksc_map;
+
+/* Per-curve flag bits reported by ksc_query_flags. */
+#define KSC_FLAG_NONFINITE 1u  /* the last J2 of the curve was NaN or Inf */
+#define KSC_FLAG_INCREASED 2u  /* J2 rose between two consecutive descent steps */
+
+/* Launch policy (ksc_set_launch). */
+#define KSC_LAUNCH_AUTO 0       /* one launch per call; tuned or default tile shape */
+#define KSC_LAUNCH_PLAIN 1      /* one launch per curve per call (reference policy) */
+#define KSC_LAUNCH_PERSISTENT 2 /* one persistent launch walking a static tile list */
+
+typedef struct {
+  int32_t n_s;   /* rows along the curve, including the two endpoint rows */
+  int32_t n_x;   /* grid points in x (power of two, 8..256) */
+  double L;      /* domain length (Sec. V.A, eq. KSE) */
+  int32_t map;   /* ksc_map */
+  double scale;  /* S (rational map) or T (finite map) */
+  double s0;     /* centre of the rational map; ignored for the finite map */
+} ksc_curve_desc;
+
+typedef struct ksc_problem ksc_problem; /* opaque */
+
+/* Create a problem for n_curves curves (descs: host array of n_curves).
+ * hip_stream: the hipStream_t every call is enqueued on (may be NULL for the
+ * default stream).  Allocates the workspace: metric and symbol tables, tile
+ * list, per-tile partials, per-curve flags.  Out: *out, freed by ksc_destroy. */
+ksc_status ksc_create(const ksc_curve_desc* descs, int32_t n_curves, int32_t dtype,
+                      void* hip_stream, ksc_problem** out);
+ksc_status ksc_destroy(ksc_problem* p);
+
+/* Change the stream later calls are enqueued on. */
+ksc_status ksc_set_stream(ksc_problem* p, void* hip_stream);
+
+/* Number of scalars (dtype elements) of a whole state / a whole physical-grid
+ * array, and the offset (in scalars) of curve c inside each. -1 on error. */
+int64_t ksc_state_numel(const ksc_problem* p);
+int64_t ksc_state_offset(const ksc_problem* p, int32_t curve);
+int64_t ksc_phys_numel(const ksc_problem* p);
+int64_t ksc_phys_offset(const ksc_problem* p, int32_t curve);
+/* Kept modes K+1 for n_x; -1 if n_x is unsupported. */
+int32_t ksc_n_modes(int32_t n_x);
+
+/* Write the two pinned endpoint rows of curve `curve` (the asymptotic states
+ * u_- and u_+ of eq. connecting_orbit_def): a_hat -> row 0, b_hat -> row
+ * n_s-1; each is K+1 interleaved complex values (device pointers). */
+ksc_status ksc_set_endpoints(ksc_problem* p, void* state, int32_t curve, const void* a_hat,
+                             const void* b_hat);
+
+/* Boundary conversions between the spectral state and physical samples on the
+ * grid x_n = n L / n_x (Sec. V.C.1).  phys: curve-major [n_s][n_x] scalars.
+ * phys_to_spec keeps modes k <= K (u_hat_k = (1/n_x) sum_n u_n e^{-2 pi i k n / n_x});
+ * spec_to_phys evaluates the band-limited field. */
+ksc_status ksc_phys_to_spec(ksc_problem* p, const void* phys, void* state);
+ksc_status ksc_spec_to_phys(ksc_problem* p, const void* state, void* phys);
+
+/* J2[c] (and J_arc[c] if Jarc != NULL) of every curve; FP64 device arrays of
+ * n_curves entries. */
+ksc_status ksc_eval_J(ksc_problem* p, const void* state, double* J2, double* Jarc);
+
+/* Euclidean gradient of J2 in the state layout, times scale[c] if scale is not
+ * NULL (FP64 device array, e.g. an autograd upstream gradient).  grad must not
+ * alias state.  J2 (nullable) receives the cost of the same evaluation. */
+ksc_status ksc_eval_grad(ksc_problem* p, const void* state, void* grad, double* J2,
+                         const double* scale);
+
+/* One descent step state_in -> state_out (distinct buffers; the endpoint rows
+ * are copied).  J2 (nullable) receives the cost of state_in. */
+ksc_status ksc_step(ksc_problem* p, const void* state_in, void* state_out, double dtau,
+                    double* J2);
+
+/* n_steps descent steps in place on `state`, ping-ponging through `scratch`
+ * (same size as the state).  Each group of `every` steps is one captured HIP
+ * graph; after each group the J2 of the group's last input state is copied to
+ * J2_trace[g * n_curves + c] (nullable; n_steps / every rows).  active
+ * (nullable, device uint8 [n_curves]): curves with 0 are left unchanged.
+ * every must be >= 1; n_steps >= 0. */
+ksc_status ksc_descend(ksc_problem* p, void* state, void* scratch, int64_t n_steps, double dtau,
+                       double* J2_trace, int32_t every, const uint8_t* active);
+
+/* Choose the launch shape (waves per tile, persistent or not) by timing the
+ * candidates on scratch buffers; the choice is cached in the JSON file at
+ * cache_path (nullable: no file) keyed by device, ROCm version and problem
+ * shape.  Blocks the host. */
+ksc_status ksc_tune(ksc_problem* p, const char* cache_path);
+
+/* Override the launch policy (KSC_LAUNCH_*) and waves per tile (1, 2 or 4;
+ * 0 keeps the current value). */
+ksc_status ksc_set_launch(ksc_problem* p, int32_t policy, int32_t waves);
+/* Current waves per tile and policy. */
+ksc_status ksc_get_launch(const ksc_problem* p, int32_t* policy, int32_t* waves);
+
+/* Copy the per-curve flag words (KSC_FLAG_*) to flags_host[n_curves] and clear
+ * them.  Synchronizes the problem's stream. */
+ksc_status ksc_query_flags(ksc_problem* p, uint32_t* flags_host);
+
+/* Message of the last failed call on this thread ("" if none). */
+const char* ksc_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* KSC_H */

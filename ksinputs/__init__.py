@@ -21,6 +21,7 @@ sigma_j = j / (n_s - 1).
 """
 from __future__ import annotations
 
+import os
 from dataclasses import dataclass, field
 
 import numpy as np
@@ -33,6 +34,7 @@ __all__ = [
     "make_curve",
     "round_to",
     "random_direction",
+    "config4_curves",
 ]
 
 
@@ -144,3 +146,29 @@ def random_direction(seed, n_s: int, n_modes: int, kmax: int = 8) -> np.ndarray:
     v[0] = 0
     v[-1] = 0
     return v
+
+
+C4_ENDPOINTS = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))),
+                            "tests", "golden", "c4_endpoints.npz")
+
+
+def config4_curves(n_curves: int = 64, n_s: int = 1024, replicas: int = 1):
+    """Workload 4: stored trajectory endpoints (A_i, B_i = Phi_20(A_i)) with the
+    blend-plus-perturbation interior, perturbation smooth(4, 0.1) seeded (4, i).
+    replicas > 1 repeats the batch (used to stream more than the caches hold).
+    Returns (specs, list of U_hat [n_s, 43])."""
+    d = np.load(C4_ENDPOINTS)
+    A, B = d["A"], d["B"]
+    specs, Us = [], []
+    base = config_specs(4, n_curves)
+    for r in range(replicas):
+        for i in range(n_curves):
+            sp = base[i]
+            if n_s != sp.n_s:
+                sp = CurveSpec(n_s, sp.n_x, sp.L, sp.kmax_end, sp.amp_end, sp.kmax_pert,
+                               sp.amp_pert, sp.random_A, sp.seed, sp.map, sp.scale, sp.s0)
+            rng = np.random.default_rng(np.random.SeedSequence([4, i, 1]))
+            p = smooth_coeffs(rng, 4, 0.1, A.shape[1])
+            specs.append(sp)
+            Us.append(blend_curve(A[i % A.shape[0]], B[i % B.shape[0]], p, n_s))
+    return specs, Us

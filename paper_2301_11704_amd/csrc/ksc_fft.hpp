@@ -1,0 +1,236 @@
+// Register-resident real <-> band-limited-spectrum transforms for one s-row
+// per lane (gfx950, wave64).
+//
+// A state row holds the Fourier coefficients X_k, k = 0..K, of a real field
+// sampled on N points, x_n = sum_{|k|<=K} X_k e^{2 pi i k n / N} (the paper's
+// spatial expansion, Sec. V.C.1), with K < N/3 so that quadratic products are
+// alias-free for the kept modes.  Each lane owns one whole row: the transform
+// runs entirely in VGPRs, twiddles are compile-time literals, and no lane ever
+// talks to another during a transform.
+//
+// Real transforms use the half-length complex trick: the N reals are paired
+// as z_m = x_{2m} + i x_{2m+1}, m < M = N/2, and one complex M-point FFT does
+// the work; an O(M) pre/post-processing step maps between Z and X.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <type_traits>
+#include <utility>
+
+namespace ksc {
+
+// ---------------------------------------------------------------------------
+// compile-time helpers
+// ---------------------------------------------------------------------------
+
+template <int... Is, class F>
+__device__ __forceinline__ void sfor_impl(std::integer_sequence<int, Is...>, F&& f) {
+  (f(std::integral_constant<int, Is>{}), ...);
+}
+// Unrolled loop whose index is a constant expression inside the body.
+template <int N, class F>
+__device__ __forceinline__ void sfor(F&& f) {
+  sfor_impl(std::make_integer_sequence<int, N>{}, f);
+}
+
+constexpr double kPi = 3.141592653589793238462643383279502884;
+
+// Taylor series of sin and cos on |x| <= pi/4 (terms to x^25; the remainder
+// is below 1e-19 there).
+constexpr double cx_sin_small(double x) {
+  double x2 = x * x, term = x, sum = x;
+  for (int n = 1; n <= 12; ++n) {
+    term *= -x2 / double((2 * n) * (2 * n + 1));
+    sum += term;
+  }
+  return sum;
+}
+constexpr double cx_cos_small(double x) {
+  double x2 = x * x, term = 1.0, sum = 1.0;
+  for (int n = 1; n <= 12; ++n) {
+    term *= -x2 / double((2 * n - 1) * (2 * n));
+    sum += term;
+  }
+  return sum;
+}
+
+// cos and sin of 2 pi e / M for integer e, with exact quadrant reduction.
+struct CS {
+  double c, s;
+};
+constexpr CS cx_unit(long e, long M) {
+  e %= M;
+  if (e < 0) e += M;
+  // quadrant q = nearest multiple of M/4; remainder angle pi * r / (2M), |r| <= M/2
+  long q = (4 * e + M / 2) / M;
+  long r = 4 * e - q * M;
+  double x = kPi * double(r) / double(2 * M);
+  double c = cx_cos_small(x), s = cx_sin_small(x);
+  switch (q & 3) {
+    case 0: return {c, s};
+    case 1: return {-s, c};
+    case 2: return {-c, -s};
+    default: return {s, -c};
+  }
+}
+
+template <typename T>
+struct cplx {
+  T r, i;
+};
+
+__device__ __forceinline__ float fmaT(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+__device__ __forceinline__ double fmaT(double a, double b, double c) { return __builtin_fma(a, b, c); }
+
+constexpr int ilog2(int n) { return n <= 1 ? 0 : 1 + ilog2(n / 2); }
+constexpr int bitrev(int v, int bits) {
+  int r = 0;
+  for (int b = 0; b < bits; ++b) r |= ((v >> b) & 1) << (bits - 1 - b);
+  return r;
+}
+
+// ---------------------------------------------------------------------------
+// complex M-point FFT in registers, radix-2 decimation in time.
+//   SIGN = -1: Z_k = sum_m z_m e^{-2 pi i k m / M}
+//   SIGN = +1: Z_k = sum_m z_m e^{+2 pi i k m / M}
+// Input in natural order, output in natural order (the bit-reversal is a
+// compile-time renaming of registers).  Butterflies with a general twiddle
+// use the 6-FMA form a' = a + w b, b' = 2a - a'.
+// ---------------------------------------------------------------------------
+template <int M, int SIGN, typename T>
+__device__ __forceinline__ void fft_c(T (&re)[M], T (&im)[M]) {
+  constexpr int LG = ilog2(M);
+  static_assert((1 << LG) == M, "power of two");
+  T xr[M], xi[M];
+  sfor<M>([&](auto I) {
+    constexpr int i = I;
+    constexpr int s = bitrev(i, LG);
+    xr[i] = re[s];
+    xi[i] = im[s];
+  });
+  sfor<LG>([&](auto S) {
+    constexpr int h = 1 << int(S);  // half-size of the sub-DFTs being merged
+    sfor<M / 2>([&](auto B) {
+      constexpr int b = B;
+      constexpr int blk = b / h, j = b % h;
+      constexpr int a0 = blk * 2 * h + j, a1 = a0 + h;
+      constexpr int e = j * (M / (2 * h));  // twiddle exponent, angle 2 pi e / M
+      if constexpr (e == 0) {
+        T tr = xr[a1], ti = xi[a1];
+        xr[a1] = xr[a0] - tr;
+        xi[a1] = xi[a0] - ti;
+        xr[a0] = xr[a0] + tr;
+        xi[a0] = xi[a0] + ti;
+      } else if constexpr (4 * e == M) {
+        // w = SIGN * i : w*b = (-SIGN b.i, SIGN b.r)
+        T tr = (SIGN > 0) ? -xi[a1] : xi[a1];
+        T ti = (SIGN > 0) ? xr[a1] : -xr[a1];
+        xr[a1] = xr[a0] - tr;
+        xi[a1] = xi[a0] - ti;
+        xr[a0] = xr[a0] + tr;
+        xi[a0] = xi[a0] + ti;
+      } else {
+        constexpr CS w = cx_unit(e, M);
+        constexpr T wr = T(w.c);
+        constexpr T wi = T(SIGN * w.s);
+        T ar = xr[a0], ai = xi[a0], br = xr[a1], bi = xi[a1];
+        T nr = fmaT(-wi, bi, fmaT(wr, br, ar));
+        T ni = fmaT(wi, br, fmaT(wr, bi, ai));
+        xr[a0] = nr;
+        xi[a0] = ni;
+        xr[a1] = fmaT(T(2), ar, -nr);
+        xi[a1] = fmaT(T(2), ai, -ni);
+      }
+    });
+  });
+  sfor<M>([&](auto I) {
+    constexpr int i = I;
+    re[i] = xr[i];
+    im[i] = xi[i];
+  });
+}
+
+// ---------------------------------------------------------------------------
+// Band-limited spectrum -> real samples.
+//   x_n = sum_{|k|<=K} X_k e^{2 pi i k n / N},  X_{-k} = conj(X_k), Im X_0 ignored.
+// X has KM = K+1 entries; out has N entries.
+// ---------------------------------------------------------------------------
+template <int N, int KM, typename T>
+__device__ __forceinline__ void spec_to_phys(const cplx<T> (&X)[KM], T (&out)[N]) {
+  constexpr int M = N / 2;
+  static_assert(KM - 1 < M, "K must be below N/2");
+  T zr[M], zi[M];
+  sfor<M>([&](auto Kk) {
+    constexpr int k = Kk;
+    constexpr int kb = M - k;  // partner index; kb == M means X_M (zero)
+    // E_k = X_k + conj(X_{M-k}),  O_k = w^k (X_k - conj(X_{M-k})),  w = e^{2 pi i / N}
+    T ar = T(0), ai = T(0), br = T(0), bi = T(0);
+    if constexpr (k < KM) {
+      ar = X[k].r;
+      ai = (k == 0) ? T(0) : X[k].i;
+    }
+    if constexpr (kb < KM) {
+      br = X[kb].r;
+      bi = -X[kb].i;  // conj
+    }
+    T er = ar + br, ei = ai + bi;
+    T dr = ar - br, di = ai - bi;
+    constexpr CS w = cx_unit(k, N);
+    constexpr T wr = T(w.c), wi = T(w.s);
+    T orr, oi;
+    if constexpr (k == 0) {
+      orr = dr;
+      oi = di;
+    } else {
+      orr = fmaT(wr, dr, -wi * di);
+      oi = fmaT(wr, di, wi * dr);
+    }
+    // Z_k = E_k + i O_k
+    zr[k] = er - oi;
+    zi[k] = ei + orr;
+  });
+  fft_c<M, +1, T>(zr, zi);
+  sfor<M>([&](auto Mm) {
+    constexpr int m = Mm;
+    out[2 * m] = zr[m];
+    out[2 * m + 1] = zi[m];
+  });
+}
+
+// ---------------------------------------------------------------------------
+// Real samples -> kept modes, scaled:
+//   X_k = scale * sum_n x_n e^{-2 pi i k n / N},  k = 0..K.
+// (scale = 1/N gives the Fourier coefficients.)  Outputs above K are never
+// formed; the dead butterflies of the last FFT stage are removed by the
+// compiler.
+// ---------------------------------------------------------------------------
+template <int N, int KM, typename T>
+__device__ __forceinline__ void phys_to_spec(const T (&x)[N], cplx<T> (&X)[KM], T scale) {
+  constexpr int M = N / 2;
+  T zr[M], zi[M];
+  sfor<M>([&](auto Mm) {
+    constexpr int m = Mm;
+    zr[m] = x[2 * m];
+    zi[m] = x[2 * m + 1];
+  });
+  fft_c<M, -1, T>(zr, zi);
+  const T hs = T(0.5) * scale;
+  sfor<KM>([&](auto Kk) {
+    constexpr int k = Kk;
+    constexpr int kb = (M - k) % M;
+    // D = Z_k + conj(Z_{M-k}) = 2 E_k,  S = Z_k - conj(Z_{M-k}) = 2 i O_k
+    T Dr = zr[k] + zr[kb], Di = zi[k] - zi[kb];
+    T Sr = zr[k] - zr[kb], Si = zi[k] + zi[kb];
+    // X_k = (E_k + w^{-k} O_k) = (D - i w^{-k} S) / 2,  w^{-k} = c - i s
+    constexpr CS w = cx_unit(k, N);
+    constexpr T c = T(w.c), s = T(w.s);
+    // -i (c - i s) = -s - i c
+    T tr = fmaT(-s, Sr, c * Si);      // Re[(-s - i c) S] = -s Sr + c Si
+    T ti = fmaT(-s, Si, -c * Sr);     // Im[(-s - i c) S] = -s Si - c Sr
+    X[k].r = (Dr + tr) * hs;
+    X[k].i = (k == 0) ? T(0) : (Di + ti) * hs;
+  });
+}
+
+}  // namespace ksc

@@ -1,0 +1,192 @@
+// Fused tile kernels for one (dtype, n_x) pair.  Compiled once per pair with
+// -DKSC_T=<float|double> -DKSC_TNAME=<f32|f64> -DKSC_NX=<8..256>, or with
+// -DKSC_MIXED for the mixed-n_x kernel.
+#include "ksc_launch.hpp"
+
+#ifndef KSC_T
+#error "KSC_T must be defined"
+#endif
+
+namespace ksc {
+
+template <int NX, typename T, int W, int MODE>
+__global__ __launch_bounds__(64 * W) void fused_kernel(KernelArgs<T> a) {
+  extern __shared__ double smem_d[];
+  constexpr int KM = (NX - 1) / 3 + 1;
+  cplx<T>* buf = reinterpret_cast<cplx<T>*>(smem_d);
+  double* red = reinterpret_cast<double*>(buf + (64 * W + 2) * KM);
+  for (int i = blockIdx.x; i < a.n_tiles; i += gridDim.x) {
+    const int tile = a.tile_base + i;
+    const TileDev td = a.tiles[tile];
+    const CurveDev cd = a.curves[td.curve];
+    if (MODE == MODE_STEP && a.active != nullptr && a.active[td.curve] == 0) {
+      tile_copy<NX, T, W>(a, cd, td.j0, tile, red);
+      continue;
+    }
+    tile_body<NX, T, W, MODE>(a, cd, td.curve, td.j0, tile, buf, red);
+  }
+}
+
+#ifdef KSC_MIXED
+template <typename T, int W, int MODE>
+__global__ __launch_bounds__(64 * W) void mixed_kernel(KernelArgs<T> a, int km_max) {
+  extern __shared__ double smem_d[];
+  cplx<T>* buf = reinterpret_cast<cplx<T>*>(smem_d);
+  double* red = reinterpret_cast<double*>(buf + (64 * W + 2) * km_max);
+  for (int i = blockIdx.x; i < a.n_tiles; i += gridDim.x) {
+    const int tile = a.tile_base + i;
+    const TileDev td = a.tiles[tile];
+    const CurveDev cd = a.curves[td.curve];
+    if (MODE == MODE_STEP && a.active != nullptr && a.active[td.curve] == 0) {
+      switch (cd.n_x) {
+        case 32: tile_copy<32, T, W>(a, cd, td.j0, tile, red); break;
+        case 64: tile_copy<64, T, W>(a, cd, td.j0, tile, red); break;
+        default: tile_copy<128, T, W>(a, cd, td.j0, tile, red); break;
+      }
+      continue;
+    }
+    switch (cd.n_x) {
+      case 32: tile_body<32, T, W, MODE>(a, cd, td.curve, td.j0, tile, buf, red); break;
+      case 64: tile_body<64, T, W, MODE>(a, cd, td.curve, td.j0, tile, buf, red); break;
+      default: tile_body<128, T, W, MODE>(a, cd, td.curve, td.j0, tile, buf, red); break;
+    }
+  }
+}
+#endif
+
+template <int NX, typename T>
+__global__ __launch_bounds__(64) void p2s_kernel(int rows, const T* __restrict__ phys,
+                                                 cplx<T>* __restrict__ spec) {
+  constexpr int KM = (NX - 1) / 3 + 1;
+  const int r = blockIdx.x * 64 + threadIdx.x;
+  if (r >= rows) return;
+  T x[NX];
+  sfor<NX>([&](auto Nn) {
+    constexpr int n = Nn;
+    x[n] = phys[(long long)r * NX + n];
+  });
+  cplx<T> X[KM];
+  phys_to_spec<NX, KM, T>(x, X, T(1) / T(NX));
+  sfor<KM>([&](auto Kk) {
+    constexpr int k = Kk;
+    spec[(long long)r * KM + k] = X[k];
+  });
+}
+
+template <int NX, typename T>
+__global__ __launch_bounds__(64) void s2p_kernel(int rows, const cplx<T>* __restrict__ spec,
+                                                 T* __restrict__ phys) {
+  constexpr int KM = (NX - 1) / 3 + 1;
+  const int r = blockIdx.x * 64 + threadIdx.x;
+  if (r >= rows) return;
+  cplx<T> X[KM];
+  sfor<KM>([&](auto Kk) {
+    constexpr int k = Kk;
+    X[k] = spec[(long long)r * KM + k];
+  });
+  T x[NX];
+  spec_to_phys<NX, KM, T>(X, x);
+  sfor<NX>([&](auto Nn) {
+    constexpr int n = Nn;
+    phys[(long long)r * NX + n] = x[n];
+  });
+}
+
+}  // namespace ksc
+
+#define KSC_CAT2(a, b) a##b
+#define KSC_CAT(a, b) KSC_CAT2(a, b)
+
+namespace ksc {
+
+#ifndef KSC_MIXED
+template <int NX, typename T, int W>
+static hipError_t launch_w(int mode, int grid, size_t lds, hipStream_t s, const KernelArgs<T>& a) {
+  switch (mode) {
+    case MODE_J:
+      hipLaunchKernelGGL((fused_kernel<NX, T, W, MODE_J>), dim3(grid), dim3(64 * W), lds, s, a);
+      break;
+    case MODE_GRAD:
+      hipLaunchKernelGGL((fused_kernel<NX, T, W, MODE_GRAD>), dim3(grid), dim3(64 * W), lds, s, a);
+      break;
+    default:
+      hipLaunchKernelGGL((fused_kernel<NX, T, W, MODE_STEP>), dim3(grid), dim3(64 * W), lds, s, a);
+      break;
+  }
+  return hipGetLastError();
+}
+
+hipError_t KSC_CAT(KSC_CAT(KSC_CAT(launch_fused_, KSC_TNAME), _), KSC_NX)(
+    int W, int mode, int grid, size_t lds, hipStream_t s, const KernelArgs<KSC_T>& a) {
+  switch (W) {
+    case 1: return launch_w<KSC_NX, KSC_T, 1>(mode, grid, lds, s, a);
+    case 2: return launch_w<KSC_NX, KSC_T, 2>(mode, grid, lds, s, a);
+    default: return launch_w<KSC_NX, KSC_T, 4>(mode, grid, lds, s, a);
+  }
+}
+
+#else
+template <typename T, int W>
+static hipError_t launch_mw(int mode, int grid, size_t lds, hipStream_t s, const KernelArgs<T>& a) {
+  const int km_max = (128 - 1) / 3 + 1;
+  switch (mode) {
+    case MODE_J:
+      hipLaunchKernelGGL((mixed_kernel<T, W, MODE_J>), dim3(grid), dim3(64 * W), lds, s, a, km_max);
+      break;
+    case MODE_GRAD:
+      hipLaunchKernelGGL((mixed_kernel<T, W, MODE_GRAD>), dim3(grid), dim3(64 * W), lds, s, a,
+                         km_max);
+      break;
+    default:
+      hipLaunchKernelGGL((mixed_kernel<T, W, MODE_STEP>), dim3(grid), dim3(64 * W), lds, s, a,
+                         km_max);
+      break;
+  }
+  return hipGetLastError();
+}
+
+hipError_t KSC_CAT(launch_mixed_, KSC_TNAME)(int W, int mode, int grid, size_t lds, hipStream_t s,
+                                            const KernelArgs<KSC_T>& a) {
+  switch (W) {
+    case 1: return launch_mw<KSC_T, 1>(mode, grid, lds, s, a);
+    case 2: return launch_mw<KSC_T, 2>(mode, grid, lds, s, a);
+    default: return launch_mw<KSC_T, 4>(mode, grid, lds, s, a);
+  }
+}
+
+template <typename T>
+static hipError_t conv(bool to_spec, int nx, int rows, hipStream_t s, const void* src, void* dst) {
+  const int g = (rows + 63) / 64;
+#define KSC_CONV_CASE(N)                                                                      \
+  case N:                                                                                     \
+    if (to_spec)                                                                              \
+      hipLaunchKernelGGL((p2s_kernel<N, T>), dim3(g), dim3(64), 0, s, rows,                   \
+                         static_cast<const T*>(src), static_cast<cplx<T>*>(dst));             \
+    else                                                                                      \
+      hipLaunchKernelGGL((s2p_kernel<N, T>), dim3(g), dim3(64), 0, s, rows,                   \
+                         static_cast<const cplx<T>*>(src), static_cast<T*>(dst));             \
+    break;
+  switch (nx) {
+    KSC_CONV_CASE(8)
+    KSC_CONV_CASE(16)
+    KSC_CONV_CASE(32)
+    KSC_CONV_CASE(64)
+    KSC_CONV_CASE(128)
+    KSC_CONV_CASE(256)
+    default: return hipErrorInvalidValue;
+  }
+#undef KSC_CONV_CASE
+  return hipGetLastError();
+}
+
+hipError_t KSC_CAT(KSC_CAT(launch_p2s_, KSC_TNAME), )(int nx, int rows, hipStream_t s,
+                                                      const KSC_T* phys, cplx<KSC_T>* spec) {
+  return conv<KSC_T>(true, nx, rows, s, phys, spec);
+}
+hipError_t KSC_CAT(KSC_CAT(launch_s2p_, KSC_TNAME), )(int nx, int rows, hipStream_t s,
+                                                      const cplx<KSC_T>* spec, KSC_T* phys) {
+  return conv<KSC_T>(false, nx, rows, s, spec, phys);
+}
+#endif
+
+}  // namespace ksc

@@ -1,0 +1,800 @@
+// Host runtime and C ABI (include/ksc.h): problem object, metric and symbol
+// tables, tile lists, launch policy, FP64 cost finalization, descent loop
+// captured as HIP graphs, launch-shape tuning.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <fstream>
+#include <sstream>
+#include <string>
+#include <vector>
+
+#include "../../include/ksc.h"
+#include "ksc_launch.hpp"
+
+using ksc::cplx;
+using ksc::CurveDev;
+using ksc::KernelArgs;
+using ksc::TileDev;
+
+namespace {
+
+thread_local std::string g_err;
+
+ksc_status fail(ksc_status st, const std::string& msg) {
+  g_err = msg;
+  return st;
+}
+
+#define KSC_HIP(call)                                                                         \
+  do {                                                                                        \
+    hipError_t e_ = (call);                                                                   \
+    if (e_ != hipSuccess)                                                                     \
+      return fail(KSC_ERR_HIP, std::string(#call) + ": " + hipGetErrorString(e_));            \
+  } while (0)
+
+bool nx_supported(int nx) {
+  return nx == 8 || nx == 16 || nx == 32 || nx == 64 || nx == 128 || nx == 256;
+}
+int modes_of(int nx) { return (nx - 1) / 3 + 1; }
+
+// ---------------------------------------------------------------- kernels --
+
+__global__ void precond_kernel(int n, const float* A, float* pre, float dtau) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) pre[i] = 1.0f / (1.0f + dtau * A[i] * A[i]);
+}
+__global__ void precond_kernel_d(int n, const double* A, double* pre, double dtau) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) pre[i] = 1.0 / (1.0 + dtau * A[i] * A[i]);
+}
+
+__device__ __forceinline__ bool finite_bits(double v) {
+  unsigned long long b = __double_as_longlong(v);
+  return ((b >> 52) & 0x7ffull) != 0x7ffull;
+}
+
+// Per-curve FP64 sums of the tile partials in tile order (deterministic).
+//   J2[c] = sum of tile costs; J_arc[c] = sqrt(L) * num / den.
+// track != 0: flag a rise of J2 against the previous call's value.
+__global__ void finalize_kernel(int n_curves, const CurveDev* curves, const double* partials,
+                                const double* sqrtL, double* J2, double* Jarc, double* prevJ2,
+                                unsigned* flags, const unsigned char* active, int track) {
+  int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= n_curves) return;
+  if (active != nullptr && active[c] == 0) return;
+  const CurveDev cd = curves[c];
+  double s0 = 0, s1 = 0, s2 = 0;
+  for (int t = 0; t < cd.n_tiles; ++t) {
+    const double* p = partials + 3ll * (cd.tile_begin + t);
+    s0 += p[0];
+    s1 += p[1];
+    s2 += p[2];
+  }
+  if (J2) J2[c] = s0;
+  if (Jarc) Jarc[c] = (s2 > 0) ? sqrtL[c] * s1 / s2 : 0.0;
+  unsigned f = 0;
+  if (!finite_bits(s0)) f |= KSC_FLAG_NONFINITE;
+  if (track) {
+    const double pv = prevJ2[c];
+    if (finite_bits(pv) && pv >= 0 && s0 > pv * (1.0 + 1e-12) + 1e-300) f |= KSC_FLAG_INCREASED;
+    prevJ2[c] = s0;
+  }
+  if (f) flags[c] |= f;
+}
+
+__global__ void copy_rows_kernel(long long n, const double* src, double* dst) {
+  long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+  if (i < n) dst[i] = src[i];
+}
+
+}  // namespace
+
+// ----------------------------------------------------------------- problem --
+
+struct ksc_problem {
+  int nc = 0;
+  int dtype = KSC_F32;
+  hipStream_t stream = nullptr;
+  int device = 0;
+  size_t lds_limit = 65536;
+  int n_cu = 256;
+
+  std::vector<ksc_curve_desc> desc;
+  std::vector<CurveDev> cd;
+  std::vector<TileDev> tiles;
+  std::vector<int> curve_order;  // curves in tile-list order (largest n_x first)
+  long long numel_c = 0;         // complex elements of the state
+  long long phys_numel = 0;
+  int rows_total = 0, modes_total = 0;
+  int max_nx = 0, min_nx = 1 << 30;
+  bool uniform = true;
+  bool mixed_ok = true;  // every n_x in {32, 64, 128}
+
+  int policy = KSC_LAUNCH_AUTO;
+  int W = 1;
+
+  // device workspace
+  CurveDev* d_cd = nullptr;
+  TileDev* d_tiles = nullptr;
+  void* d_cs = nullptr;
+  void* d_wlT = nullptr;
+  double* d_wlD = nullptr;
+  void* d_q = nullptr;
+  void* d_A = nullptr;
+  void* d_pre = nullptr;
+  double* d_sqrtL = nullptr;
+  double* d_part = nullptr;
+  double* d_prevJ2 = nullptr;
+  unsigned* d_flags = nullptr;
+  double* d_J2 = nullptr;
+  int part_cap = 0;
+  double pre_dtau = std::nan("");
+
+  // descent graph cache
+  hipStream_t cap_stream = nullptr;
+  hipGraphExec_t gexec = nullptr;
+  hipGraph_t graph = nullptr;
+  struct Key {
+    void* state = nullptr;
+    void* scratch = nullptr;
+    double dtau = 0;
+    int every = 0;
+    const void* active = nullptr;
+    int W = 0, policy = 0;
+    hipStream_t stream = nullptr;
+  } gkey;
+
+  size_t esize() const { return dtype == KSC_F64 ? 8 : 4; }
+};
+
+namespace {
+
+int rows_per_tile(int W) { return 64 * W - 2; }
+
+size_t lds_bytes(const ksc_problem* p, int W, int km) {
+  const size_t cs = 2 * p->esize();
+  return size_t(64 * W + 2) * km * cs + 3 * W * sizeof(double);
+}
+
+// Largest W in {4, 2, 1} (at most `cap`) whose staging buffer fits in LDS.
+int fit_W(const ksc_problem* p, int cap, int km) {
+  for (int W : {4, 2, 1})
+    if (W <= cap && lds_bytes(p, W, km) <= p->lds_limit) return W;
+  return 0;
+}
+
+int default_W(const ksc_problem* p) {
+  // Small grids: 4 waves per tile; the largest grids: 1 wave (LDS and registers).
+  int km = modes_of(p->max_nx);
+  int cap = p->max_nx <= 64 ? 4 : (p->max_nx <= 128 ? 2 : 1);
+  return fit_W(p, cap, km);
+}
+
+ksc_status build_tiles(ksc_problem* p) {
+  const int R = rows_per_tile(p->W);
+  p->tiles.clear();
+  for (int c : p->curve_order) {
+    CurveDev& d = p->cd[c];
+    const int nt = (d.n_s - 2 + R - 1) / R;
+    d.tile_begin = int(p->tiles.size());
+    d.n_tiles = nt;
+    for (int i = 0; i < nt; ++i) p->tiles.push_back(TileDev{c, 1 + i * R});
+  }
+  if (p->d_tiles) hipFree(p->d_tiles);
+  p->d_tiles = nullptr;
+  KSC_HIP(hipMalloc(&p->d_tiles, p->tiles.size() * sizeof(TileDev)));
+  KSC_HIP(hipMemcpy(p->d_tiles, p->tiles.data(), p->tiles.size() * sizeof(TileDev),
+                    hipMemcpyHostToDevice));
+  KSC_HIP(hipMemcpy(p->d_cd, p->cd.data(), p->cd.size() * sizeof(CurveDev),
+                    hipMemcpyHostToDevice));
+  if (int(p->tiles.size()) > p->part_cap) {
+    if (p->d_part) hipFree(p->d_part);
+    p->d_part = nullptr;
+    p->part_cap = int(p->tiles.size());
+    KSC_HIP(hipMalloc(&p->d_part, 3 * sizeof(double) * p->part_cap));
+  }
+  return KSC_OK;
+}
+
+void drop_graph(ksc_problem* p) {
+  if (p->gexec) hipGraphExecDestroy(p->gexec);
+  if (p->graph) hipGraphDestroy(p->graph);
+  p->gexec = nullptr;
+  p->graph = nullptr;
+}
+
+template <typename T>
+hipError_t launch_uniform(int nx, int W, int mode, int grid, size_t lds, hipStream_t s,
+                          const KernelArgs<T>& a);
+
+template <>
+hipError_t launch_uniform<float>(int nx, int W, int mode, int grid, size_t lds, hipStream_t s,
+                                 const KernelArgs<float>& a) {
+  switch (nx) {
+    case 8: return ksc::launch_fused_f32_8(W, mode, grid, lds, s, a);
+    case 16: return ksc::launch_fused_f32_16(W, mode, grid, lds, s, a);
+    case 32: return ksc::launch_fused_f32_32(W, mode, grid, lds, s, a);
+    case 64: return ksc::launch_fused_f32_64(W, mode, grid, lds, s, a);
+    case 128: return ksc::launch_fused_f32_128(W, mode, grid, lds, s, a);
+    default: return ksc::launch_fused_f32_256(W, mode, grid, lds, s, a);
+  }
+}
+template <>
+hipError_t launch_uniform<double>(int nx, int W, int mode, int grid, size_t lds, hipStream_t s,
+                                  const KernelArgs<double>& a) {
+  switch (nx) {
+    case 8: return ksc::launch_fused_f64_8(W, mode, grid, lds, s, a);
+    case 16: return ksc::launch_fused_f64_16(W, mode, grid, lds, s, a);
+    case 32: return ksc::launch_fused_f64_32(W, mode, grid, lds, s, a);
+    case 64: return ksc::launch_fused_f64_64(W, mode, grid, lds, s, a);
+    case 128: return ksc::launch_fused_f64_128(W, mode, grid, lds, s, a);
+    default: return ksc::launch_fused_f64_256(W, mode, grid, lds, s, a);
+  }
+}
+hipError_t launch_mixed(const KernelArgs<float>& a, int W, int mode, int grid, size_t lds,
+                        hipStream_t s) {
+  return ksc::launch_mixed_f32(W, mode, grid, lds, s, a);
+}
+hipError_t launch_mixed(const KernelArgs<double>& a, int W, int mode, int grid, size_t lds,
+                        hipStream_t s) {
+  return ksc::launch_mixed_f64(W, mode, grid, lds, s, a);
+}
+
+template <typename T>
+KernelArgs<T> make_args(ksc_problem* p, const void* in, void* out, const double* scale,
+                        const uint8_t* active, double dtau) {
+  KernelArgs<T> a{};
+  a.in = static_cast<const cplx<T>*>(in);
+  a.out = static_cast<cplx<T>*>(out);
+  a.curves = p->d_cd;
+  a.tiles = p->d_tiles;
+  a.cs = static_cast<const T*>(p->d_cs);
+  a.wlT = static_cast<const T*>(p->d_wlT);
+  a.wlD = p->d_wlD;
+  a.q = static_cast<const T*>(p->d_q);
+  a.A = static_cast<const T*>(p->d_A);
+  a.pre = static_cast<const T*>(p->d_pre);
+  a.scale = scale;
+  a.active = active;
+  a.partials = p->d_part;
+  a.dtau = T(dtau);
+  a.n_tiles = int(p->tiles.size());
+  a.tile_base = 0;
+  return a;
+}
+
+// Enqueue the fused kernel(s) for `mode` on stream s according to the policy.
+template <typename T>
+ksc_status launch_fused(ksc_problem* p, int mode, const void* in, void* out, const double* scale,
+                        const uint8_t* active, double dtau, hipStream_t s) {
+  KernelArgs<T> a = make_args<T>(p, in, out, scale, active, dtau);
+  const int W = p->W;
+  if (p->policy == KSC_LAUNCH_PLAIN) {
+    for (int c = 0; c < p->nc; ++c) {
+      const CurveDev& d = p->cd[c];
+      KernelArgs<T> ac = a;
+      ac.tile_base = d.tile_begin;
+      ac.n_tiles = d.n_tiles;
+      const size_t lds = lds_bytes(p, W, d.km);
+      hipError_t e = launch_uniform<T>(d.n_x, W, mode, d.n_tiles, lds, s, ac);
+      if (e != hipSuccess) return fail(KSC_ERR_HIP, std::string("launch: ") + hipGetErrorString(e));
+    }
+    return KSC_OK;
+  }
+  const int nt = int(p->tiles.size());
+  int grid = nt;
+  if (p->policy == KSC_LAUNCH_PERSISTENT) grid = std::min(nt, p->n_cu * (W == 1 ? 4 : 2));
+  if (p->uniform) {
+    const size_t lds = lds_bytes(p, W, modes_of(p->max_nx));
+    hipError_t e = launch_uniform<T>(p->max_nx, W, mode, grid, lds, s, a);
+    if (e != hipSuccess) return fail(KSC_ERR_HIP, std::string("launch: ") + hipGetErrorString(e));
+    return KSC_OK;
+  }
+  if (p->mixed_ok) {
+    const size_t lds = lds_bytes(p, W, modes_of(128));
+    hipError_t e = launch_mixed(a, W, mode, grid, lds, s);
+    if (e != hipSuccess) return fail(KSC_ERR_HIP, std::string("launch: ") + hipGetErrorString(e));
+    return KSC_OK;
+  }
+  // Other mixtures: one launch per distinct n_x over that group's tiles
+  // (tiles of a group are contiguous because curves are ordered by n_x).
+  int t0 = 0;
+  while (t0 < nt) {
+    const int nx = p->cd[p->tiles[t0].curve].n_x;
+    int t1 = t0;
+    while (t1 < nt && p->cd[p->tiles[t1].curve].n_x == nx) ++t1;
+    KernelArgs<T> ag = a;
+    ag.tile_base = t0;
+    ag.n_tiles = t1 - t0;
+    const size_t lds = lds_bytes(p, W, modes_of(nx));
+    hipError_t e = launch_uniform<T>(nx, W, mode, t1 - t0, lds, s, ag);
+    if (e != hipSuccess) return fail(KSC_ERR_HIP, std::string("launch: ") + hipGetErrorString(e));
+    t0 = t1;
+  }
+  return KSC_OK;
+}
+
+ksc_status launch_fused_any(ksc_problem* p, int mode, const void* in, void* out,
+                            const double* scale, const uint8_t* active, double dtau,
+                            hipStream_t s) {
+  if (p->dtype == KSC_F64) return launch_fused<double>(p, mode, in, out, scale, active, dtau, s);
+  return launch_fused<float>(p, mode, in, out, scale, active, dtau, s);
+}
+
+ksc_status finalize(ksc_problem* p, double* J2, double* Jarc, const uint8_t* active, int track,
+                    hipStream_t s) {
+  const int b = 64, g = (p->nc + b - 1) / b;
+  hipLaunchKernelGGL(finalize_kernel, dim3(g), dim3(b), 0, s, p->nc, p->d_cd, p->d_part,
+                     p->d_sqrtL, J2, Jarc, p->d_prevJ2, p->d_flags, active, track);
+  KSC_HIP(hipGetLastError());
+  return KSC_OK;
+}
+
+ksc_status ensure_pre(ksc_problem* p, double dtau, hipStream_t s) {
+  if (p->pre_dtau == dtau) return KSC_OK;
+  const int n = p->modes_total, b = 256, g = (n + b - 1) / b;
+  if (p->dtype == KSC_F64)
+    hipLaunchKernelGGL(precond_kernel_d, dim3(g), dim3(b), 0, s, n,
+                       static_cast<const double*>(p->d_A), static_cast<double*>(p->d_pre), dtau);
+  else
+    hipLaunchKernelGGL(precond_kernel, dim3(g), dim3(b), 0, s, n,
+                       static_cast<const float*>(p->d_A), static_cast<float*>(p->d_pre),
+                       float(dtau));
+  KSC_HIP(hipGetLastError());
+  p->pre_dtau = dtau;
+  return KSC_OK;
+}
+
+template <typename T>
+std::vector<T> cast_vec(const std::vector<double>& v) {
+  return std::vector<T>(v.begin(), v.end());
+}
+
+}  // namespace
+
+// ------------------------------------------------------------------- C ABI --
+
+extern "C" {
+
+const char* ksc_last_error(void) { return g_err.c_str(); }
+
+int32_t ksc_n_modes(int32_t n_x) { return nx_supported(n_x) ? modes_of(n_x) : -1; }
+
+ksc_status ksc_create(const ksc_curve_desc* descs, int32_t n_curves, int32_t dtype,
+                      void* hip_stream, ksc_problem** out) {
+  g_err.clear();
+  if (!descs || !out) return fail(KSC_ERR_ARG, "ksc_create: null pointer");
+  *out = nullptr;
+  if (n_curves < 1) return fail(KSC_ERR_SHAPE, "ksc_create: n_curves must be >= 1");
+  if (dtype != KSC_F32 && dtype != KSC_F64) return fail(KSC_ERR_ARG, "ksc_create: bad dtype");
+  for (int c = 0; c < n_curves; ++c) {
+    const ksc_curve_desc& d = descs[c];
+    if (!nx_supported(d.n_x))
+      return fail(KSC_ERR_UNSUPPORTED, "ksc_create: curve " + std::to_string(c) + ": n_x=" +
+                                           std::to_string(d.n_x) + " not in {8,...,256}");
+    if (d.n_s < 3)
+      return fail(KSC_ERR_SHAPE, "ksc_create: curve " + std::to_string(c) + ": n_s < 3");
+    if (d.n_s > (1 << 26))
+      return fail(KSC_ERR_SHAPE, "ksc_create: curve " + std::to_string(c) + ": n_s too large");
+    if (!(d.L > 0) || !std::isfinite(d.L))
+      return fail(KSC_ERR_ARG, "ksc_create: curve " + std::to_string(c) + ": L must be > 0");
+    if (d.map != KSC_MAP_RATIONAL && d.map != KSC_MAP_FINITE)
+      return fail(KSC_ERR_ARG, "ksc_create: curve " + std::to_string(c) + ": bad map");
+    if (!(d.scale > 0) || !std::isfinite(d.scale))
+      return fail(KSC_ERR_ARG, "ksc_create: curve " + std::to_string(c) + ": scale must be > 0");
+    if (!std::isfinite(d.s0)) return fail(KSC_ERR_ARG, "ksc_create: s0 must be finite");
+  }
+  auto* p = new ksc_problem();
+  p->nc = n_curves;
+  p->dtype = dtype;
+  p->stream = static_cast<hipStream_t>(hip_stream);
+  p->desc.assign(descs, descs + n_curves);
+  auto cleanup = [&](ksc_status st) {
+    ksc_destroy(p);
+    return st;
+  };
+  if (hipGetDevice(&p->device) != hipSuccess) return cleanup(fail(KSC_ERR_HIP, "no HIP device"));
+  hipDeviceProp_t prop;
+  if (hipGetDeviceProperties(&prop, p->device) != hipSuccess)
+    return cleanup(fail(KSC_ERR_HIP, "hipGetDeviceProperties failed"));
+  p->lds_limit = prop.sharedMemPerBlock;
+  p->n_cu = prop.multiProcessorCount;
+
+  // layout, tables (FP64 on the host, cast to the run precision)
+  std::vector<double> cs, wl, q, A, sqrtL;
+  p->cd.resize(n_curves);
+  for (int c = 0; c < n_curves; ++c) {
+    const ksc_curve_desc& d = descs[c];
+    CurveDev& cd = p->cd[c];
+    cd.n_s = d.n_s;
+    cd.n_x = d.n_x;
+    cd.km = modes_of(d.n_x);
+    cd.off = p->numel_c;
+    cd.poff = p->phys_numel;
+    cd.row_off = int(cs.size());
+    cd.mode_off = int(q.size());
+    p->numel_c += (long long)d.n_s * cd.km;
+    p->phys_numel += (long long)d.n_s * d.n_x;
+    const double dsig = 1.0 / (d.n_s - 1);
+    for (int j = 0; j < d.n_s; ++j) {
+      double g;
+      if (d.map == KSC_MAP_RATIONAL) {
+        const double th = M_PI * (1.0 - j * dsig);
+        const double sn = std::sin(th);
+        g = sn * sn / (M_PI * d.scale);
+      } else {
+        g = 1.0 / d.scale;
+      }
+      const bool interior = (j > 0 && j < d.n_s - 1);
+      cs.push_back(interior ? g / (2.0 * dsig) : 0.0);
+      wl.push_back(interior ? dsig / g * d.L : 0.0);
+    }
+    for (int k = 0; k < cd.km; ++k) {
+      const double qk = 2.0 * M_PI * k / d.L;
+      q.push_back(qk);
+      A.push_back(qk * qk - qk * qk * qk * qk);
+    }
+    sqrtL.push_back(std::sqrt(d.L));
+    p->max_nx = std::max(p->max_nx, d.n_x);
+    p->min_nx = std::min(p->min_nx, d.n_x);
+    if (d.n_x != 32 && d.n_x != 64 && d.n_x != 128) p->mixed_ok = false;
+  }
+  p->uniform = (p->max_nx == p->min_nx);
+  p->rows_total = int(cs.size());
+  p->modes_total = int(q.size());
+  p->curve_order.resize(n_curves);
+  for (int c = 0; c < n_curves; ++c) p->curve_order[c] = c;
+  std::stable_sort(p->curve_order.begin(), p->curve_order.end(),
+                   [&](int a, int b) { return p->cd[a].n_x > p->cd[b].n_x; });
+
+  const size_t es = p->esize();
+  auto upload = [&](void** dst, const std::vector<double>& v) -> ksc_status {
+    KSC_HIP(hipMalloc(dst, std::max<size_t>(1, v.size()) * es));
+    if (p->dtype == KSC_F64) {
+      KSC_HIP(hipMemcpy(*dst, v.data(), v.size() * 8, hipMemcpyHostToDevice));
+    } else {
+      std::vector<float> f = cast_vec<float>(v);
+      KSC_HIP(hipMemcpy(*dst, f.data(), f.size() * 4, hipMemcpyHostToDevice));
+    }
+    return KSC_OK;
+  };
+  ksc_status st;
+  if ((st = upload(&p->d_cs, cs)) != KSC_OK) return cleanup(st);
+  if ((st = upload(&p->d_wlT, wl)) != KSC_OK) return cleanup(st);
+  if ((st = upload(&p->d_q, q)) != KSC_OK) return cleanup(st);
+  if ((st = upload(&p->d_A, A)) != KSC_OK) return cleanup(st);
+  if ((st = upload(&p->d_pre, A)) != KSC_OK) return cleanup(st);  // overwritten per dtau
+  auto upload_d = [&](double** dst, const std::vector<double>& v) -> ksc_status {
+    KSC_HIP(hipMalloc(dst, std::max<size_t>(1, v.size()) * 8));
+    KSC_HIP(hipMemcpy(*dst, v.data(), v.size() * 8, hipMemcpyHostToDevice));
+    return KSC_OK;
+  };
+  if ((st = upload_d(&p->d_wlD, wl)) != KSC_OK) return cleanup(st);
+  if ((st = upload_d(&p->d_sqrtL, sqrtL)) != KSC_OK) return cleanup(st);
+  if (hipMalloc(&p->d_cd, n_curves * sizeof(CurveDev)) != hipSuccess ||
+      hipMalloc(&p->d_prevJ2, n_curves * sizeof(double)) != hipSuccess ||
+      hipMalloc(&p->d_J2, n_curves * sizeof(double)) != hipSuccess ||
+      hipMalloc(&p->d_flags, n_curves * sizeof(unsigned)) != hipSuccess)
+    return cleanup(fail(KSC_ERR_HIP, "ksc_create: workspace allocation failed"));
+  if (hipMemset(p->d_flags, 0, n_curves * sizeof(unsigned)) != hipSuccess)
+    return cleanup(fail(KSC_ERR_HIP, "ksc_create: hipMemset failed"));
+  {
+    std::vector<double> nanv(n_curves, std::nan(""));
+    if (hipMemcpy(p->d_prevJ2, nanv.data(), n_curves * 8, hipMemcpyHostToDevice) != hipSuccess)
+      return cleanup(fail(KSC_ERR_HIP, "ksc_create: hipMemcpy failed"));
+  }
+  p->W = default_W(p);
+  if (p->W == 0)
+    return cleanup(fail(KSC_ERR_UNSUPPORTED, "ksc_create: tile staging buffer exceeds LDS"));
+  if ((st = build_tiles(p)) != KSC_OK) return cleanup(st);
+  if (hipStreamCreateWithFlags(&p->cap_stream, hipStreamNonBlocking) != hipSuccess)
+    return cleanup(fail(KSC_ERR_HIP, "ksc_create: stream creation failed"));
+  *out = p;
+  return KSC_OK;
+}
+
+ksc_status ksc_destroy(ksc_problem* p) {
+  if (!p) return fail(KSC_ERR_ARG, "ksc_destroy: null problem");
+  drop_graph(p);
+  if (p->cap_stream) hipStreamDestroy(p->cap_stream);
+  void* bufs[] = {p->d_cd, p->d_tiles, p->d_cs,     p->d_wlT,    p->d_wlD,   p->d_q,
+                  p->d_A,  p->d_pre,   p->d_sqrtL,  p->d_part,   p->d_prevJ2, p->d_flags,
+                  p->d_J2};
+  for (void* b : bufs)
+    if (b) hipFree(b);
+  delete p;
+  return KSC_OK;
+}
+
+ksc_status ksc_set_stream(ksc_problem* p, void* hip_stream) {
+  if (!p) return fail(KSC_ERR_ARG, "ksc_set_stream: null problem");
+  p->stream = static_cast<hipStream_t>(hip_stream);
+  return KSC_OK;
+}
+
+int64_t ksc_state_numel(const ksc_problem* p) { return p ? 2 * p->numel_c : -1; }
+int64_t ksc_state_offset(const ksc_problem* p, int32_t c) {
+  if (!p || c < 0 || c >= p->nc) return -1;
+  return 2 * p->cd[c].off;
+}
+int64_t ksc_phys_numel(const ksc_problem* p) { return p ? p->phys_numel : -1; }
+int64_t ksc_phys_offset(const ksc_problem* p, int32_t c) {
+  if (!p || c < 0 || c >= p->nc) return -1;
+  return p->cd[c].poff;
+}
+
+ksc_status ksc_set_endpoints(ksc_problem* p, void* state, int32_t curve, const void* a_hat,
+                             const void* b_hat) {
+  if (!p || !state || !a_hat || !b_hat) return fail(KSC_ERR_ARG, "ksc_set_endpoints: null pointer");
+  if (curve < 0 || curve >= p->nc) return fail(KSC_ERR_SHAPE, "ksc_set_endpoints: bad curve");
+  const CurveDev& d = p->cd[curve];
+  const size_t rowb = size_t(d.km) * 2 * p->esize();
+  char* base = static_cast<char*>(state) + d.off * 2 * p->esize();
+  KSC_HIP(hipMemcpyAsync(base, a_hat, rowb, hipMemcpyDeviceToDevice, p->stream));
+  KSC_HIP(hipMemcpyAsync(base + size_t(d.n_s - 1) * rowb, b_hat, rowb, hipMemcpyDeviceToDevice,
+                         p->stream));
+  return KSC_OK;
+}
+
+static ksc_status convert(ksc_problem* p, bool to_spec, const void* src, void* dst) {
+  if (!p || !src || !dst) return fail(KSC_ERR_ARG, "conversion: null pointer");
+  for (int c = 0; c < p->nc; ++c) {
+    const CurveDev& d = p->cd[c];
+    hipError_t e;
+    if (p->dtype == KSC_F64) {
+      const double* ph = static_cast<const double*>(to_spec ? src : dst) + d.poff;
+      cplx<double>* sp = reinterpret_cast<cplx<double>*>(const_cast<void*>(to_spec ? dst : src)) + d.off;
+      e = to_spec ? ksc::launch_p2s_f64(d.n_x, d.n_s, p->stream, ph, sp)
+                  : ksc::launch_s2p_f64(d.n_x, d.n_s, p->stream, sp, const_cast<double*>(ph));
+    } else {
+      const float* ph = static_cast<const float*>(to_spec ? src : dst) + d.poff;
+      cplx<float>* sp = reinterpret_cast<cplx<float>*>(const_cast<void*>(to_spec ? dst : src)) + d.off;
+      e = to_spec ? ksc::launch_p2s_f32(d.n_x, d.n_s, p->stream, ph, sp)
+                  : ksc::launch_s2p_f32(d.n_x, d.n_s, p->stream, sp, const_cast<float*>(ph));
+    }
+    if (e != hipSuccess) return fail(KSC_ERR_HIP, std::string("conversion: ") + hipGetErrorString(e));
+  }
+  return KSC_OK;
+}
+
+ksc_status ksc_phys_to_spec(ksc_problem* p, const void* phys, void* state) {
+  return convert(p, true, phys, state);
+}
+ksc_status ksc_spec_to_phys(ksc_problem* p, const void* state, void* phys) {
+  return convert(p, false, state, phys);
+}
+
+ksc_status ksc_eval_J(ksc_problem* p, const void* state, double* J2, double* Jarc) {
+  if (!p || !state || !J2) return fail(KSC_ERR_ARG, "ksc_eval_J: null pointer");
+  ksc_status st = launch_fused_any(p, ksc::MODE_J, state, nullptr, nullptr, nullptr, 0.0, p->stream);
+  if (st != KSC_OK) return st;
+  return finalize(p, J2, Jarc, nullptr, 0, p->stream);
+}
+
+ksc_status ksc_eval_grad(ksc_problem* p, const void* state, void* grad, double* J2,
+                         const double* scale) {
+  if (!p || !state || !grad) return fail(KSC_ERR_ARG, "ksc_eval_grad: null pointer");
+  if (grad == state) return fail(KSC_ERR_ARG, "ksc_eval_grad: grad must not alias state");
+  ksc_status st = launch_fused_any(p, ksc::MODE_GRAD, state, grad, scale, nullptr, 0.0, p->stream);
+  if (st != KSC_OK) return st;
+  if (J2) return finalize(p, J2, nullptr, nullptr, 0, p->stream);
+  return KSC_OK;
+}
+
+ksc_status ksc_step(ksc_problem* p, const void* in, void* out, double dtau, double* J2) {
+  if (!p || !in || !out) return fail(KSC_ERR_ARG, "ksc_step: null pointer");
+  if (in == out) return fail(KSC_ERR_ARG, "ksc_step: in and out must differ");
+  if (!(dtau > 0) || !std::isfinite(dtau)) return fail(KSC_ERR_ARG, "ksc_step: dtau must be > 0");
+  ksc_status st = ensure_pre(p, dtau, p->stream);
+  if (st != KSC_OK) return st;
+  st = launch_fused_any(p, ksc::MODE_STEP, in, out, nullptr, nullptr, dtau, p->stream);
+  if (st != KSC_OK) return st;
+  if (J2) return finalize(p, J2, nullptr, nullptr, 0, p->stream);
+  return KSC_OK;
+}
+
+// Record `every` steps (state -> scratch -> state ...) plus per-step
+// finalization into one graph on the capture stream.
+static ksc_status capture_descent(ksc_problem* p, void* state, void* scratch, double dtau,
+                                  int every, const uint8_t* active) {
+  drop_graph(p);
+  hipStream_t s = p->cap_stream;
+  KSC_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+  ksc_status st = KSC_OK;
+  for (int i = 0; i < every && st == KSC_OK; ++i) {
+    const void* in = (i % 2 == 0) ? state : scratch;
+    void* out = (i % 2 == 0) ? scratch : state;
+    st = launch_fused_any(p, ksc::MODE_STEP, in, out, nullptr, active, dtau, s);
+    if (st == KSC_OK) st = finalize(p, p->d_J2, nullptr, active, 1, s);
+  }
+  hipGraph_t g = nullptr;
+  hipError_t e = hipStreamEndCapture(s, &g);
+  if (st != KSC_OK) {
+    if (g) hipGraphDestroy(g);
+    return st;
+  }
+  if (e != hipSuccess) return fail(KSC_ERR_HIP, std::string("capture: ") + hipGetErrorString(e));
+  p->graph = g;
+  e = hipGraphInstantiate(&p->gexec, g, nullptr, nullptr, 0);
+  if (e != hipSuccess) {
+    drop_graph(p);
+    return fail(KSC_ERR_HIP, std::string("instantiate: ") + hipGetErrorString(e));
+  }
+  p->gkey = ksc_problem::Key{state, scratch, dtau, every, active, p->W, p->policy, p->stream};
+  return KSC_OK;
+}
+
+ksc_status ksc_descend(ksc_problem* p, void* state, void* scratch, int64_t n_steps, double dtau,
+                       double* J2_trace, int32_t every, const uint8_t* active) {
+  if (!p || !state || !scratch) return fail(KSC_ERR_ARG, "ksc_descend: null pointer");
+  if (state == scratch) return fail(KSC_ERR_ARG, "ksc_descend: scratch must differ from state");
+  if (n_steps < 0) return fail(KSC_ERR_ARG, "ksc_descend: n_steps < 0");
+  if (every < 1) return fail(KSC_ERR_ARG, "ksc_descend: every must be >= 1");
+  if (!(dtau > 0) || !std::isfinite(dtau)) return fail(KSC_ERR_ARG, "ksc_descend: dtau must be > 0");
+  if (n_steps == 0) return KSC_OK;
+  ksc_status st = ensure_pre(p, dtau, p->stream);
+  if (st != KSC_OK) return st;
+  // the endpoint rows of scratch must match the state's: copy the whole state once
+  KSC_HIP(hipMemcpyAsync(scratch, state, size_t(2 * p->numel_c) * p->esize(),
+                         hipMemcpyDeviceToDevice, p->stream));
+  // groups of `every` steps; an odd group ends in scratch and is copied back
+  const int G = every;
+  const ksc_problem::Key want{state, scratch, dtau, G, active, p->W, p->policy, p->stream};
+  const bool same = p->gexec && want.state == p->gkey.state && want.scratch == p->gkey.scratch &&
+                    want.dtau == p->gkey.dtau && want.every == p->gkey.every &&
+                    want.active == p->gkey.active && want.W == p->gkey.W &&
+                    want.policy == p->gkey.policy;
+  if (!same) {
+    // the capture stream must not run ahead of work already queued on p->stream
+    KSC_HIP(hipStreamSynchronize(p->stream));
+    if ((st = capture_descent(p, state, scratch, dtau, G, active)) != KSC_OK) return st;
+  }
+  const int64_t groups = n_steps / G;
+  const int64_t rem = n_steps % G;
+  for (int64_t gi = 0; gi < groups; ++gi) {
+    KSC_HIP(hipGraphLaunch(p->gexec, p->stream));
+    if (G % 2 == 1)
+      KSC_HIP(hipMemcpyAsync(state, scratch, size_t(2 * p->numel_c) * p->esize(),
+                             hipMemcpyDeviceToDevice, p->stream));
+    if (J2_trace)
+      KSC_HIP(hipMemcpyAsync(J2_trace + gi * p->nc, p->d_J2, p->nc * sizeof(double),
+                             hipMemcpyDeviceToDevice, p->stream));
+  }
+  for (int64_t i = 0; i < rem; ++i) {
+    const void* in = (i % 2 == 0) ? state : scratch;
+    void* out = (i % 2 == 0) ? scratch : state;
+    st = launch_fused_any(p, ksc::MODE_STEP, in, out, nullptr, active, dtau, p->stream);
+    if (st != KSC_OK) return st;
+    if ((st = finalize(p, p->d_J2, nullptr, active, 1, p->stream)) != KSC_OK) return st;
+  }
+  if (rem % 2 == 1)
+    KSC_HIP(hipMemcpyAsync(state, scratch, size_t(2 * p->numel_c) * p->esize(),
+                           hipMemcpyDeviceToDevice, p->stream));
+  return KSC_OK;
+}
+
+ksc_status ksc_set_launch(ksc_problem* p, int32_t policy, int32_t waves) {
+  if (!p) return fail(KSC_ERR_ARG, "ksc_set_launch: null problem");
+  if (policy != KSC_LAUNCH_AUTO && policy != KSC_LAUNCH_PLAIN && policy != KSC_LAUNCH_PERSISTENT)
+    return fail(KSC_ERR_ARG, "ksc_set_launch: bad policy");
+  if (waves != 0 && waves != 1 && waves != 2 && waves != 4)
+    return fail(KSC_ERR_ARG, "ksc_set_launch: waves must be 0, 1, 2 or 4");
+  if (waves != 0) {
+    int km = modes_of(p->max_nx);
+    if (!p->uniform && p->mixed_ok) km = modes_of(128);
+    if (lds_bytes(p, waves, km) > p->lds_limit)
+      return fail(KSC_ERR_UNSUPPORTED, "ksc_set_launch: tile does not fit in LDS");
+    if (waves != p->W) {
+      p->W = waves;
+      ksc_status st = build_tiles(p);
+      if (st != KSC_OK) return st;
+      drop_graph(p);
+    }
+  }
+  if (policy != p->policy) drop_graph(p);
+  p->policy = policy;
+  return KSC_OK;
+}
+
+ksc_status ksc_get_launch(const ksc_problem* p, int32_t* policy, int32_t* waves) {
+  if (!p || !policy || !waves) return fail(KSC_ERR_ARG, "ksc_get_launch: null pointer");
+  *policy = p->policy;
+  *waves = p->W;
+  return KSC_OK;
+}
+
+ksc_status ksc_query_flags(ksc_problem* p, uint32_t* flags_host) {
+  if (!p || !flags_host) return fail(KSC_ERR_ARG, "ksc_query_flags: null pointer");
+  KSC_HIP(hipStreamSynchronize(p->stream));
+  KSC_HIP(hipMemcpy(flags_host, p->d_flags, p->nc * sizeof(unsigned), hipMemcpyDeviceToHost));
+  KSC_HIP(hipMemset(p->d_flags, 0, p->nc * sizeof(unsigned)));
+  return KSC_OK;
+}
+
+// Time each admissible (policy, W) on scratch state buffers and keep the
+// fastest for J + gradient; the result is cached in a small JSON file.
+ksc_status ksc_tune(ksc_problem* p, const char* cache_path) {
+  if (!p) return fail(KSC_ERR_ARG, "ksc_tune: null problem");
+  hipDeviceProp_t prop;
+  KSC_HIP(hipGetDeviceProperties(&prop, p->device));
+  int rt = 0;
+  hipRuntimeGetVersion(&rt);
+  std::ostringstream key;
+  key << prop.gcnArchName << "|" << rt << "|" << (p->dtype == KSC_F64 ? "f64" : "f32") << "|";
+  for (const auto& d : p->desc) key << d.n_x << "x" << d.n_s << ";";
+  std::string kstr = key.str();
+  // a long key is hashed to keep the file small
+  if (kstr.size() > 200) {
+    unsigned long long h = 1469598103934665603ull;
+    for (char ch : kstr) h = (h ^ (unsigned char)ch) * 1099511628211ull;
+    kstr = kstr.substr(0, 64) + "#" + std::to_string(h);
+  }
+  if (cache_path) {
+    std::ifstream f(cache_path);
+    std::string line;
+    while (std::getline(f, line)) {
+      auto pos = line.find("\"" + kstr + "\"");
+      if (pos == std::string::npos) continue;
+      int pol = 0, w = 0;
+      auto pp = line.find("\"policy\":", pos), pw = line.find("\"waves\":", pos);
+      if (pp != std::string::npos && pw != std::string::npos) {
+        pol = std::atoi(line.c_str() + pp + 9);
+        w = std::atoi(line.c_str() + pw + 8);
+        return ksc_set_launch(p, pol, w);
+      }
+    }
+  }
+  const size_t bytes = size_t(2 * p->numel_c) * p->esize();
+  void *x = nullptr, *g = nullptr;
+  double* j2 = nullptr;
+  KSC_HIP(hipMalloc(&x, bytes));
+  KSC_HIP(hipMalloc(&g, bytes));
+  KSC_HIP(hipMalloc(&j2, p->nc * sizeof(double)));
+  KSC_HIP(hipMemsetAsync(x, 0, bytes, p->stream));
+  hipEvent_t e0, e1;
+  KSC_HIP(hipEventCreate(&e0));
+  KSC_HIP(hipEventCreate(&e1));
+  int best_pol = p->policy, best_w = p->W;
+  float best = 1e30f;
+  int km = modes_of(p->max_nx);
+  if (!p->uniform && p->mixed_ok) km = modes_of(128);
+  for (int pol : {KSC_LAUNCH_AUTO, KSC_LAUNCH_PERSISTENT}) {
+    for (int w : {1, 2, 4}) {
+      if (lds_bytes(p, w, km) > p->lds_limit) continue;
+      if (ksc_set_launch(p, pol, w) != KSC_OK) continue;
+      ksc_eval_grad(p, x, g, j2, nullptr);  // warm-up
+      hipEventRecord(e0, p->stream);
+      const int reps = 10;
+      for (int r = 0; r < reps; ++r) ksc_eval_grad(p, x, g, j2, nullptr);
+      hipEventRecord(e1, p->stream);
+      hipEventSynchronize(e1);
+      float ms = 0;
+      hipEventElapsedTime(&ms, e0, e1);
+      if (ms < best) {
+        best = ms;
+        best_pol = pol;
+        best_w = w;
+      }
+    }
+  }
+  hipEventDestroy(e0);
+  hipEventDestroy(e1);
+  hipFree(x);
+  hipFree(g);
+  hipFree(j2);
+  ksc_status st = ksc_set_launch(p, best_pol, best_w);
+  if (st != KSC_OK) return st;
+  if (cache_path) {
+    std::ofstream f(cache_path, std::ios::app);
+    f << "{\"" << kstr << "\": {\"policy\": " << best_pol << ", \"waves\": " << best_w
+      << ", \"ms_per_eval\": " << best / 10 << "}}\n";
+  }
+  return KSC_OK;
+}
+
+}  // extern "C"

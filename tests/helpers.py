@@ -1,0 +1,51 @@
+"""Shared helpers of the parity tests: seeded curves, oracle evaluation and the
+parity metrics.  The gradient metric compares L2 gradients (Euclidean
+gradient divided by 2 w_j L c_k) in the norm weighted by 1/(1 + A_k^2) per
+mode, since FP64 implementations that differ only in transform rounding
+already disagree in the unweighted norm at the large-A_k modes."""
+from __future__ import annotations
+
+import numpy as np
+
+import ksinputs
+import oracle
+
+
+def oracle_curve(spec: ksinputs.CurveSpec) -> oracle.Curve:
+    return oracle.Curve(spec.n_s, spec.n_x, spec.L, spec.map, spec.scale, spec.s0)
+
+
+def seeded_state(spec: ksinputs.CurveSpec, dtype) -> np.ndarray:
+    """The seeded curve rounded to the run precision (both sides consume it)."""
+    K1 = oracle.n_modes(spec.n_x)
+    _, _, U = ksinputs.make_curve(spec, K1)
+    U[:, 0] = U[:, 0].real
+    return ksinputs.round_to(U, dtype)
+
+
+def l2_gradient(c: oracle.Curve, G: np.ndarray) -> np.ndarray:
+    """Euclidean gradient -> L2 gradient (L^dagger r) on interior rows."""
+    w = c.w[1:-1, None] * c.L * c.c[None, :]
+    return G[1:-1] / (2.0 * w)
+
+
+def precond_rel_err(c: oracle.Curve, G_test: np.ndarray, G_ref: np.ndarray) -> float:
+    Pi = 1.0 / (1.0 + c.A ** 2)
+    a = l2_gradient(c, G_test) * Pi[None, :]
+    b = l2_gradient(c, G_ref) * Pi[None, :]
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+def directional_rel_err(c: oracle.Curve, G_test: np.ndarray, G_ref: np.ndarray, seeds) -> float:
+    """max over seeded smooth directions V of the error of the directional
+    derivative <G, V> relative to its condition, sum |G_ref| |V| (the size of the
+    terms the dot product adds up; a plain |<G_ref, V>| can cancel to a few
+    percent of that and then measures cancellation, not the gradient)."""
+    worst = 0.0
+    for s in seeds:
+        V = ksinputs.random_direction(s, c.n_s, c.K + 1)
+        dref = float(np.sum(G_ref.real * V.real + G_ref.imag * V.imag))
+        dtest = float(np.sum(G_test.real * V.real + G_test.imag * V.imag))
+        mag = float(np.sum(np.abs(G_ref.real * V.real) + np.abs(G_ref.imag * V.imag)))
+        worst = max(worst, abs(dtest - dref) / mag)
+    return worst

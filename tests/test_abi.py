@@ -1,0 +1,47 @@
+"""The C-ABI library loads and exports every symbol include/ksc.h declares
+(CPU only: no call that touches a device)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "ksc.h")
+
+
+def _declared():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(ksc_[A-Za-z0-9_]+)\s*\(", src)))
+
+
+def test_header_declares_the_binding_set():
+    from paper_2301_11704_amd import _lib
+    assert _declared() == sorted(_lib.EXPORTED)
+
+
+def test_library_exports_every_declared_symbol():
+    from paper_2301_11704_amd import _lib
+    if not os.path.exists(_lib.LIB_PATH):
+        pytest.skip("libksc.so not built")
+    L = ctypes.CDLL(_lib.LIB_PATH)
+    for name in _declared():
+        assert hasattr(L, name), name
+
+
+def test_pure_host_calls():
+    from paper_2301_11704_amd import _lib
+    if not os.path.exists(_lib.LIB_PATH):
+        pytest.skip("libksc.so not built")
+    L = _lib.lib()
+    for nx, km in ((8, 3), (16, 6), (32, 11), (64, 22), (128, 43), (256, 86)):
+        assert L.ksc_n_modes(nx) == km
+    for bad in (0, 7, 48, 512):
+        assert L.ksc_n_modes(bad) == -1
+    # null-pointer validation happens before any HIP call
+    assert L.ksc_create(None, 1, 0, None, None) == -1
+    assert b"null" in L.ksc_last_error()
+    assert L.ksc_destroy(None) == -1
+    assert L.ksc_state_numel(None) == -1
+    assert L.ksc_eval_J(None, None, None, None) == -1
