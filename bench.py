@@ -108,6 +108,9 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the host oracle baseline")
     ap.add_argument("--no-extras", action="store_true", help="skip plain and streaming legs")
     ap.add_argument("--replicas", type=int, default=48, help="streaming-leg replication factor")
+    ap.add_argument("--copy-probe", type=float, default=0.0, metavar="GB",
+                    help="only run one plain device-to-device copy of this many GB (calibrates "
+                         "the HBM byte counters) and exit")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the batched path "
@@ -115,9 +118,19 @@ def main():
         sys.exit(2)
 
     import torch
-    import paper_2301_11704_amd as ksc
 
     torch.cuda.set_device(0)
+    if args.copy_probe > 0:
+        n = int(args.copy_probe * 1e9) // 4
+        a = torch.ones(n, dtype=torch.float32, device="cuda")
+        b = torch.empty_like(a)
+        torch.cuda.synchronize()
+        b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_probe_bytes_read": 4 * n, "copy_probe_bytes_written": 4 * n}))
+        return
+
+    import paper_2301_11704_amd as ksc
     stream = torch.cuda.current_stream()
     specs, Us, _ = _specs_and_states(args.workload)
     descs = [ksc.CurveDesc(s.n_s, s.n_x, s.L, s.map, s.scale, s.s0) for s in specs]

@@ -199,14 +199,15 @@ __device__ __forceinline__ void spec_to_phys(const cplx<T> (&X)[KM], T (&out)[N]
 }
 
 // ---------------------------------------------------------------------------
-// Real samples -> kept modes, scaled:
-//   X_k = scale * sum_n x_n e^{-2 pi i k n / N},  k = 0..K.
-// (scale = 1/N gives the Fourier coefficients.)  Outputs above K are never
+// Real samples -> kept modes, unnormalized and doubled:
+//   X_k = 2 * sum_n x_n e^{-2 pi i k n / N},  k = 0..K
+// (X_k / (2N) is the Fourier coefficient; callers fold 1/(2N) into the
+// per-mode constants they multiply by anyway).  Outputs above K are never
 // formed; the dead butterflies of the last FFT stage are removed by the
 // compiler.
 // ---------------------------------------------------------------------------
 template <int N, int KM, typename T>
-__device__ __forceinline__ void phys_to_spec(const T (&x)[N], cplx<T> (&X)[KM], T scale) {
+__device__ __forceinline__ void phys_to_spec2(const T (&x)[N], cplx<T> (&X)[KM]) {
   constexpr int M = N / 2;
   T zr[M], zi[M];
   sfor<M>([&](auto Mm) {
@@ -215,21 +216,34 @@ __device__ __forceinline__ void phys_to_spec(const T (&x)[N], cplx<T> (&X)[KM], 
     zi[m] = x[2 * m + 1];
   });
   fft_c<M, -1, T>(zr, zi);
-  const T hs = T(0.5) * scale;
   sfor<KM>([&](auto Kk) {
     constexpr int k = Kk;
     constexpr int kb = (M - k) % M;
     // D = Z_k + conj(Z_{M-k}) = 2 E_k,  S = Z_k - conj(Z_{M-k}) = 2 i O_k
-    T Dr = zr[k] + zr[kb], Di = zi[k] - zi[kb];
-    T Sr = zr[k] - zr[kb], Si = zi[k] + zi[kb];
-    // X_k = (E_k + w^{-k} O_k) = (D - i w^{-k} S) / 2,  w^{-k} = c - i s
+    // 2 (E_k + w^{-k} O_k) = D - i w^{-k} S,  w^{-k} = c - i s,  -i (c - i s) = -s - i c
     constexpr CS w = cx_unit(k, N);
     constexpr T c = T(w.c), s = T(w.s);
-    // -i (c - i s) = -s - i c
-    T tr = fmaT(-s, Sr, c * Si);      // Re[(-s - i c) S] = -s Sr + c Si
-    T ti = fmaT(-s, Si, -c * Sr);     // Im[(-s - i c) S] = -s Si - c Sr
-    X[k].r = (Dr + tr) * hs;
-    X[k].i = (k == 0) ? T(0) : (Di + ti) * hs;
+    if constexpr (k == 0) {
+      X[0].r = (zr[0] + zr[0]) + (zi[0] + zi[0]);
+      X[0].i = T(0);
+    } else {
+      const T Dr = zr[k] + zr[kb], Di = zi[k] - zi[kb];
+      const T Sr = zr[k] - zr[kb], Si = zi[k] + zi[kb];
+      X[k].r = fmaT(-s, Sr, fmaT(c, Si, Dr));
+      X[k].i = fmaT(-s, Si, fmaT(-c, Sr, Di));
+    }
+  });
+}
+
+// Real samples -> Fourier coefficients X_k = (1/N) sum_n x_n e^{-2 pi i k n / N}.
+template <int N, int KM, typename T>
+__device__ __forceinline__ void phys_to_spec(const T (&x)[N], cplx<T> (&X)[KM]) {
+  phys_to_spec2<N, KM, T>(x, X);
+  constexpr T h = T(0.5 / N);
+  sfor<KM>([&](auto Kk) {
+    constexpr int k = Kk;
+    X[k].r *= h;
+    X[k].i *= h;
   });
 }
 

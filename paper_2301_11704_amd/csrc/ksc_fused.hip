@@ -29,10 +29,10 @@ __global__ __launch_bounds__(64 * W) void fused_kernel(KernelArgs<T> a) {
 
 #ifdef KSC_MIXED
 template <typename T, int W, int MODE>
-__global__ __launch_bounds__(64 * W) void mixed_kernel(KernelArgs<T> a, int km_max) {
+__global__ __launch_bounds__(64 * W) void mixed_kernel(KernelArgs<T> a) {
   extern __shared__ double smem_d[];
   cplx<T>* buf = reinterpret_cast<cplx<T>*>(smem_d);
-  double* red = reinterpret_cast<double*>(buf + (64 * W + 2) * km_max);
+  double* red = reinterpret_cast<double*>(buf + (64 * W + 2) * ((128 - 1) / 3 + 1));
   for (int i = blockIdx.x; i < a.n_tiles; i += gridDim.x) {
     const int tile = a.tile_base + i;
     const TileDev td = a.tiles[tile];
@@ -66,7 +66,7 @@ __global__ __launch_bounds__(64) void p2s_kernel(int rows, const T* __restrict__
     x[n] = phys[(long long)r * NX + n];
   });
   cplx<T> X[KM];
-  phys_to_spec<NX, KM, T>(x, X, T(1) / T(NX));
+  phys_to_spec<NX, KM, T>(x, X);
   sfor<KM>([&](auto Kk) {
     constexpr int k = Kk;
     spec[(long long)r * KM + k] = X[k];
@@ -99,9 +99,19 @@ __global__ __launch_bounds__(64) void s2p_kernel(int rows, const cplx<T>* __rest
 
 namespace ksc {
 
+// Tile shapes whose LDS staging buffer exceeds the 160 KB of a gfx950 CU are
+// not instantiated.
+template <typename T, int W, int KM>
+constexpr bool tile_fits() {
+  return (64 * W + 2) * KM * int(sizeof(cplx<T>)) + 3 * W * 8 <= 160 * 1024;
+}
+
 #ifndef KSC_MIXED
 template <int NX, typename T, int W>
 static hipError_t launch_w(int mode, int grid, size_t lds, hipStream_t s, const KernelArgs<T>& a) {
+  if constexpr (!tile_fits<T, W, (NX - 1) / 3 + 1>()) {
+    return hipErrorInvalidValue;
+  } else {
   switch (mode) {
     case MODE_J:
       hipLaunchKernelGGL((fused_kernel<NX, T, W, MODE_J>), dim3(grid), dim3(64 * W), lds, s, a);
@@ -114,6 +124,7 @@ static hipError_t launch_w(int mode, int grid, size_t lds, hipStream_t s, const 
       break;
   }
   return hipGetLastError();
+  }
 }
 
 hipError_t KSC_CAT(KSC_CAT(KSC_CAT(launch_fused_, KSC_TNAME), _), KSC_NX)(
@@ -128,21 +139,22 @@ hipError_t KSC_CAT(KSC_CAT(KSC_CAT(launch_fused_, KSC_TNAME), _), KSC_NX)(
 #else
 template <typename T, int W>
 static hipError_t launch_mw(int mode, int grid, size_t lds, hipStream_t s, const KernelArgs<T>& a) {
-  const int km_max = (128 - 1) / 3 + 1;
+  if constexpr (!tile_fits<T, W, (128 - 1) / 3 + 1>()) {
+    return hipErrorInvalidValue;
+  } else {
   switch (mode) {
     case MODE_J:
-      hipLaunchKernelGGL((mixed_kernel<T, W, MODE_J>), dim3(grid), dim3(64 * W), lds, s, a, km_max);
+      hipLaunchKernelGGL((mixed_kernel<T, W, MODE_J>), dim3(grid), dim3(64 * W), lds, s, a);
       break;
     case MODE_GRAD:
-      hipLaunchKernelGGL((mixed_kernel<T, W, MODE_GRAD>), dim3(grid), dim3(64 * W), lds, s, a,
-                         km_max);
+      hipLaunchKernelGGL((mixed_kernel<T, W, MODE_GRAD>), dim3(grid), dim3(64 * W), lds, s, a);
       break;
     default:
-      hipLaunchKernelGGL((mixed_kernel<T, W, MODE_STEP>), dim3(grid), dim3(64 * W), lds, s, a,
-                         km_max);
+      hipLaunchKernelGGL((mixed_kernel<T, W, MODE_STEP>), dim3(grid), dim3(64 * W), lds, s, a);
       break;
   }
   return hipGetLastError();
+  }
 }
 
 hipError_t KSC_CAT(launch_mixed_, KSC_TNAME)(int W, int mode, int grid, size_t lds, hipStream_t s,

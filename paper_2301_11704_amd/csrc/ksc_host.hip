@@ -46,11 +46,11 @@ int modes_of(int nx) { return (nx - 1) / 3 + 1; }
 
 __global__ void precond_kernel(int n, const float* A, float* pre, float dtau) {
   int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) pre[i] = 1.0f / (1.0f + dtau * A[i] * A[i]);
+  if (i < n) pre[i] = -dtau / (1.0f + dtau * A[i] * A[i]);
 }
 __global__ void precond_kernel_d(int n, const double* A, double* pre, double dtau) {
   int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) pre[i] = 1.0 / (1.0 + dtau * A[i] * A[i]);
+  if (i < n) pre[i] = -dtau / (1.0 + dtau * A[i] * A[i]);
 }
 
 __device__ __forceinline__ bool finite_bits(double v) {
@@ -58,38 +58,112 @@ __device__ __forceinline__ bool finite_bits(double v) {
   return ((b >> 52) & 0x7ffull) != 0x7ffull;
 }
 
-// Per-curve FP64 sums of the tile partials in tile order (deterministic).
-//   J2[c] = sum of tile costs; J_arc[c] = sqrt(L) * num / den.
-// track != 0: flag a rise of J2 against the previous call's value.
-__global__ void finalize_kernel(int n_curves, const CurveDev* curves, const double* partials,
-                                const double* sqrtL, double* J2, double* Jarc, double* prevJ2,
-                                unsigned* flags, const unsigned char* active, int track) {
-  int c = blockIdx.x * blockDim.x + threadIdx.x;
-  if (c >= n_curves) return;
-  if (active != nullptr && active[c] == 0) return;
-  const CurveDev cd = curves[c];
-  double s0 = 0, s1 = 0, s2 = 0;
-  for (int t = 0; t < cd.n_tiles; ++t) {
-    const double* p = partials + 3ll * (cd.tile_begin + t);
-    s0 += p[0];
-    s1 += p[1];
-    s2 += p[2];
-  }
-  if (J2) J2[c] = s0;
-  if (Jarc) Jarc[c] = (s2 > 0) ? sqrtL[c] * s1 / s2 : 0.0;
-  unsigned f = 0;
-  if (!finite_bits(s0)) f |= KSC_FLAG_NONFINITE;
-  if (track) {
-    const double pv = prevJ2[c];
-    if (finite_bits(pv) && pv >= 0 && s0 > pv * (1.0 + 1e-12) + 1e-300) f |= KSC_FLAG_INCREASED;
-    prevJ2[c] = s0;
-  }
-  if (f) flags[c] |= f;
+template <typename T>
+struct PostArgs {
+  int nc;
+  const CurveDev* curves;
+  const TileDev* tiles;
+  int n_tiles;
+  const double* partials;
+  const double* sqrtL;
+  double* J2;            // nullable
+  double* Jarc;          // nullable
+  double* prevJ2;
+  unsigned* flags;
+  const unsigned char* active;
+  int track;
+  int fin_blocks;        // blocks [0, fin_blocks): one wave per curve reduces its cost
+  int mode;              // MODE_GRAD / MODE_STEP: finish the tile-boundary rows
+  int rows_per_tile;
+  int km_max;
+  const cplx<T>* edge;
+  const cplx<T>* in;
+  cplx<T>* out;
+  const T* cs;
+  const T* wlT;
+  const T* pre;
+  const double* scale;
+};
+
+// Fixed-shape butterfly sum over a wave: every lane ends with the same value,
+// and the order of additions does not depend on timing (deterministic).
+__device__ __forceinline__ double wave_sum_fixed(double v) {
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
 }
 
-__global__ void copy_rows_kernel(long long n, const double* src, double* dst) {
-  long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x;
-  if (i < n) dst[i] = src[i];
+// Runs after every fused launch (256 threads per block).
+//  * blocks [0, fin_blocks): one wave per curve loads its tiles' FP64 partials
+//    in parallel (lane i takes tiles i, i+64, ...) and sums them with a fixed
+//    reduction tree into J2 and J_arc = sqrt(L) num/den; raises the curve's
+//    flags (non-finite cost; with track, a rise of the cost).
+//  * the other blocks: one thread per (tile boundary, mode) completes the two
+//    boundary rows L | F = L+1 of a curve, whose neighbouring residual row was
+//    computed by the other tile:  adj_L += cs_L r_F,  adj_F -= cs_F r_L, and
+//    writes the gradient or the stepped state of both rows.
+template <typename T>
+__global__ __launch_bounds__(256) void post_kernel(PostArgs<T> a) {
+  if (int(blockIdx.x) < a.fin_blocks) {
+    const int c = blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    if (c >= a.nc) return;
+    if (a.active != nullptr && a.active[c] == 0) return;
+    const CurveDev cd = a.curves[c];
+    double s0 = 0, s1 = 0, s2 = 0;
+    for (int t = lane; t < cd.n_tiles; t += 64) {
+      const double* p = a.partials + 3ll * (cd.tile_begin + t);
+      s0 += p[0];
+      s1 += p[1];
+      s2 += p[2];
+    }
+    s0 = wave_sum_fixed(s0);
+    s1 = wave_sum_fixed(s1);
+    s2 = wave_sum_fixed(s2);
+    if (lane != 0) return;
+    if (a.J2) a.J2[c] = s0;
+    if (a.Jarc) a.Jarc[c] = (s2 > 0) ? a.sqrtL[c] * s1 / s2 : 0.0;
+    unsigned f = 0;
+    if (!finite_bits(s0)) f |= KSC_FLAG_NONFINITE;
+    if (a.track) {
+      const double pv = a.prevJ2[c];
+      if (finite_bits(pv) && pv >= 0 && s0 > pv * (1.0 + 1e-12) + 1e-300) f |= KSC_FLAG_INCREASED;
+      a.prevJ2[c] = s0;
+    }
+    if (f) a.flags[c] |= f;
+    return;
+  }
+  const long long g = (long long)(blockIdx.x - a.fin_blocks) * blockDim.x + threadIdx.x;
+  const int t = int(g / a.km_max), k = int(g % a.km_max);
+  if (t >= a.n_tiles - 1) return;
+  const TileDev td = a.tiles[t];
+  const int c = td.curve;
+  const CurveDev cd = a.curves[c];
+  if (k >= cd.km) return;
+  if (a.active != nullptr && a.active[c] == 0) return;
+  const int L = td.j0 + a.rows_per_tile - 1, F = L + 1;
+  if (!(L >= 1 && F <= cd.n_s - 2)) return;
+  const long long km = a.km_max;
+  const cplx<T> pL = a.edge[(t * 4ll + 2) * km + k], rL = a.edge[(t * 4ll + 3) * km + k];
+  const cplx<T> pF = a.edge[((t + 1) * 4ll + 0) * km + k], rF = a.edge[((t + 1) * 4ll + 1) * km + k];
+  const T csL = a.cs[cd.row_off + L], csF = a.cs[cd.row_off + F];
+  const T aLr = pL.r + csL * rF.r, aLi = pL.i + csL * rF.i;
+  const T aFr = pF.r - csF * rL.r, aFi = pF.i - csF * rL.i;
+  cplx<T>* oL = a.out + cd.off + (long long)L * cd.km + k;
+  cplx<T>* oF = a.out + cd.off + (long long)F * cd.km + k;
+  if (a.mode == ksc::MODE_GRAD) {
+    const T sc = a.scale ? T(a.scale[c]) : T(1);
+    const T ck = (k == 0) ? T(1) : T(2);
+    const T fL = ck * a.wlT[cd.row_off + L] * sc, fF = ck * a.wlT[cd.row_off + F] * sc;
+    *oL = cplx<T>{fL * aLr, (k == 0) ? T(0) : fL * aLi};
+    *oF = cplx<T>{fF * aFr, (k == 0) ? T(0) : fF * aFi};
+  } else {
+    const T pk = a.pre[cd.mode_off + k];
+    const cplx<T> xL = a.in[cd.off + (long long)L * cd.km + k];
+    const cplx<T> xF = a.in[cd.off + (long long)F * cd.km + k];
+    *oL = cplx<T>{xL.r + pk * aLr, (k == 0) ? T(0) : xL.i + pk * aLi};
+    *oF = cplx<T>{xF.r + pk * aFr, (k == 0) ? T(0) : xF.i + pk * aFi};
+  }
 }
 
 }  // namespace
@@ -124,8 +198,11 @@ struct ksc_problem {
   void* d_cs = nullptr;
   void* d_wlT = nullptr;
   double* d_wlD = nullptr;
-  void* d_q = nullptr;
+  void* d_qN = nullptr;
+  void* d_qY = nullptr;
   void* d_A = nullptr;
+  void* d_edge = nullptr;
+  int km_max = 0;
   void* d_pre = nullptr;
   double* d_sqrtL = nullptr;
   double* d_part = nullptr;
@@ -154,7 +231,7 @@ struct ksc_problem {
 
 namespace {
 
-int rows_per_tile(int W) { return 64 * W - 2; }
+int rows_per_tile(int W) { return 64 * W; }
 
 size_t lds_bytes(const ksc_problem* p, int W, int km) {
   const size_t cs = 2 * p->esize();
@@ -169,10 +246,11 @@ int fit_W(const ksc_problem* p, int cap, int km) {
 }
 
 int default_W(const ksc_problem* p) {
-  // Small grids: 4 waves per tile; the largest grids: 1 wave (LDS and registers).
+  // The widest tile whose staging buffer fits: 256 rows per tile keeps the
+  // tile count of a 1024-row curve at exactly 4.
   int km = modes_of(p->max_nx);
-  int cap = p->max_nx <= 64 ? 4 : (p->max_nx <= 128 ? 2 : 1);
-  return fit_W(p, cap, km);
+  if (!p->uniform && p->mixed_ok) km = modes_of(128);
+  return fit_W(p, 4, km);
 }
 
 ksc_status build_tiles(ksc_problem* p) {
@@ -180,10 +258,10 @@ ksc_status build_tiles(ksc_problem* p) {
   p->tiles.clear();
   for (int c : p->curve_order) {
     CurveDev& d = p->cd[c];
-    const int nt = (d.n_s - 2 + R - 1) / R;
+    const int nt = (d.n_s + R - 1) / R;
     d.tile_begin = int(p->tiles.size());
     d.n_tiles = nt;
-    for (int i = 0; i < nt; ++i) p->tiles.push_back(TileDev{c, 1 + i * R});
+    for (int i = 0; i < nt; ++i) p->tiles.push_back(TileDev{c, i * R});
   }
   if (p->d_tiles) hipFree(p->d_tiles);
   p->d_tiles = nullptr;
@@ -194,9 +272,12 @@ ksc_status build_tiles(ksc_problem* p) {
                     hipMemcpyHostToDevice));
   if (int(p->tiles.size()) > p->part_cap) {
     if (p->d_part) hipFree(p->d_part);
+    if (p->d_edge) hipFree(p->d_edge);
     p->d_part = nullptr;
+    p->d_edge = nullptr;
     p->part_cap = int(p->tiles.size());
     KSC_HIP(hipMalloc(&p->d_part, 3 * sizeof(double) * p->part_cap));
+    KSC_HIP(hipMalloc(&p->d_edge, size_t(p->part_cap) * 4 * p->km_max * 2 * p->esize()));
   }
   return KSC_OK;
 }
@@ -247,7 +328,7 @@ hipError_t launch_mixed(const KernelArgs<double>& a, int W, int mode, int grid, 
 
 template <typename T>
 KernelArgs<T> make_args(ksc_problem* p, const void* in, void* out, const double* scale,
-                        const uint8_t* active, double dtau) {
+                        const uint8_t* active) {
   KernelArgs<T> a{};
   a.in = static_cast<const cplx<T>*>(in);
   a.out = static_cast<cplx<T>*>(out);
@@ -256,13 +337,15 @@ KernelArgs<T> make_args(ksc_problem* p, const void* in, void* out, const double*
   a.cs = static_cast<const T*>(p->d_cs);
   a.wlT = static_cast<const T*>(p->d_wlT);
   a.wlD = p->d_wlD;
-  a.q = static_cast<const T*>(p->d_q);
+  a.qN = static_cast<const T*>(p->d_qN);
+  a.qY = static_cast<const T*>(p->d_qY);
   a.A = static_cast<const T*>(p->d_A);
   a.pre = static_cast<const T*>(p->d_pre);
   a.scale = scale;
   a.active = active;
   a.partials = p->d_part;
-  a.dtau = T(dtau);
+  a.edge = static_cast<cplx<T>*>(p->d_edge);
+  a.km_max = p->km_max;
   a.n_tiles = int(p->tiles.size());
   a.tile_base = 0;
   return a;
@@ -271,8 +354,8 @@ KernelArgs<T> make_args(ksc_problem* p, const void* in, void* out, const double*
 // Enqueue the fused kernel(s) for `mode` on stream s according to the policy.
 template <typename T>
 ksc_status launch_fused(ksc_problem* p, int mode, const void* in, void* out, const double* scale,
-                        const uint8_t* active, double dtau, hipStream_t s) {
-  KernelArgs<T> a = make_args<T>(p, in, out, scale, active, dtau);
+                        const uint8_t* active, hipStream_t s) {
+  KernelArgs<T> a = make_args<T>(p, in, out, scale, active);
   const int W = p->W;
   if (p->policy == KSC_LAUNCH_PLAIN) {
     for (int c = 0; c < p->nc; ++c) {
@@ -319,20 +402,59 @@ ksc_status launch_fused(ksc_problem* p, int mode, const void* in, void* out, con
   return KSC_OK;
 }
 
-ksc_status launch_fused_any(ksc_problem* p, int mode, const void* in, void* out,
-                            const double* scale, const uint8_t* active, double dtau,
-                            hipStream_t s) {
-  if (p->dtype == KSC_F64) return launch_fused<double>(p, mode, in, out, scale, active, dtau, s);
-  return launch_fused<float>(p, mode, in, out, scale, active, dtau, s);
-}
-
-ksc_status finalize(ksc_problem* p, double* J2, double* Jarc, const uint8_t* active, int track,
-                    hipStream_t s) {
-  const int b = 64, g = (p->nc + b - 1) / b;
-  hipLaunchKernelGGL(finalize_kernel, dim3(g), dim3(b), 0, s, p->nc, p->d_cd, p->d_part,
-                     p->d_sqrtL, J2, Jarc, p->d_prevJ2, p->d_flags, active, track);
+template <typename T>
+ksc_status launch_post(ksc_problem* p, int mode, const void* in, void* out, const double* scale,
+                       const uint8_t* active, double* J2, double* Jarc, int track,
+                       bool finalize, hipStream_t s) {
+  PostArgs<T> a{};
+  a.nc = p->nc;
+  a.curves = p->d_cd;
+  a.tiles = p->d_tiles;
+  a.n_tiles = int(p->tiles.size());
+  a.partials = p->d_part;
+  a.sqrtL = p->d_sqrtL;
+  a.J2 = J2;
+  a.Jarc = Jarc;
+  a.prevJ2 = p->d_prevJ2;
+  a.flags = p->d_flags;
+  a.active = active;
+  a.track = track;
+  const int b = 256;
+  a.fin_blocks = finalize ? (p->nc + 3) / 4 : 0;
+  a.mode = mode;
+  a.rows_per_tile = rows_per_tile(p->W);
+  a.km_max = p->km_max;
+  a.edge = static_cast<const cplx<T>*>(p->d_edge);
+  a.in = static_cast<const cplx<T>*>(in);
+  a.out = static_cast<cplx<T>*>(out);
+  a.cs = static_cast<const T*>(p->d_cs);
+  a.wlT = static_cast<const T*>(p->d_wlT);
+  a.pre = static_cast<const T*>(p->d_pre);
+  a.scale = scale;
+  const long long nfix = (mode == ksc::MODE_J) ? 0 : (long long)a.n_tiles * p->km_max;
+  const int fix_blocks = int((nfix + b - 1) / b);
+  const int grid = a.fin_blocks + fix_blocks;
+  if (grid == 0) return KSC_OK;
+  hipLaunchKernelGGL(post_kernel<T>, dim3(grid), dim3(b), 0, s, a);
   KSC_HIP(hipGetLastError());
   return KSC_OK;
+}
+
+// One evaluation: the fused tile kernel(s) and the post kernel.
+ksc_status run(ksc_problem* p, int mode, const void* in, void* out, const double* scale,
+               const uint8_t* active, double* J2, double* Jarc, int track, bool finalize,
+               hipStream_t s) {
+  ksc_status st;
+  if (p->dtype == KSC_F64) {
+    st = launch_fused<double>(p, mode, in, out, scale, active, s);
+    if (st == KSC_OK)
+      st = launch_post<double>(p, mode, in, out, scale, active, J2, Jarc, track, finalize, s);
+  } else {
+    st = launch_fused<float>(p, mode, in, out, scale, active, s);
+    if (st == KSC_OK)
+      st = launch_post<float>(p, mode, in, out, scale, active, J2, Jarc, track, finalize, s);
+  }
+  return st;
 }
 
 ksc_status ensure_pre(ksc_problem* p, double dtau, hipStream_t s) {
@@ -406,7 +528,7 @@ ksc_status ksc_create(const ksc_curve_desc* descs, int32_t n_curves, int32_t dty
   p->n_cu = prop.multiProcessorCount;
 
   // layout, tables (FP64 on the host, cast to the run precision)
-  std::vector<double> cs, wl, q, A, sqrtL;
+  std::vector<double> cs, wl, wl2, qN, qY, A, sqrtL;
   p->cd.resize(n_curves);
   for (int c = 0; c < n_curves; ++c) {
     const ksc_curve_desc& d = descs[c];
@@ -417,7 +539,7 @@ ksc_status ksc_create(const ksc_curve_desc* descs, int32_t n_curves, int32_t dty
     cd.off = p->numel_c;
     cd.poff = p->phys_numel;
     cd.row_off = int(cs.size());
-    cd.mode_off = int(q.size());
+    cd.mode_off = int(A.size());
     p->numel_c += (long long)d.n_s * cd.km;
     p->phys_numel += (long long)d.n_s * d.n_x;
     const double dsig = 1.0 / (d.n_s - 1);
@@ -433,10 +555,13 @@ ksc_status ksc_create(const ksc_curve_desc* descs, int32_t n_curves, int32_t dty
       const bool interior = (j > 0 && j < d.n_s - 1);
       cs.push_back(interior ? g / (2.0 * dsig) : 0.0);
       wl.push_back(interior ? dsig / g * d.L : 0.0);
+      wl2.push_back(interior ? 2.0 * dsig / g * d.L : 0.0);
     }
     for (int k = 0; k < cd.km; ++k) {
       const double qk = 2.0 * M_PI * k / d.L;
-      q.push_back(qk);
+      // the r2c kernels return 2 N_x times the Fourier coefficients
+      qN.push_back(qk / (4.0 * d.n_x));
+      qY.push_back(qk / (2.0 * d.n_x));
       A.push_back(qk * qk - qk * qk * qk * qk);
     }
     sqrtL.push_back(std::sqrt(d.L));
@@ -446,7 +571,8 @@ ksc_status ksc_create(const ksc_curve_desc* descs, int32_t n_curves, int32_t dty
   }
   p->uniform = (p->max_nx == p->min_nx);
   p->rows_total = int(cs.size());
-  p->modes_total = int(q.size());
+  p->modes_total = int(A.size());
+  p->km_max = modes_of(p->max_nx);
   p->curve_order.resize(n_curves);
   for (int c = 0; c < n_curves; ++c) p->curve_order[c] = c;
   std::stable_sort(p->curve_order.begin(), p->curve_order.end(),
@@ -465,8 +591,9 @@ ksc_status ksc_create(const ksc_curve_desc* descs, int32_t n_curves, int32_t dty
   };
   ksc_status st;
   if ((st = upload(&p->d_cs, cs)) != KSC_OK) return cleanup(st);
-  if ((st = upload(&p->d_wlT, wl)) != KSC_OK) return cleanup(st);
-  if ((st = upload(&p->d_q, q)) != KSC_OK) return cleanup(st);
+  if ((st = upload(&p->d_wlT, wl2)) != KSC_OK) return cleanup(st);
+  if ((st = upload(&p->d_qN, qN)) != KSC_OK) return cleanup(st);
+  if ((st = upload(&p->d_qY, qY)) != KSC_OK) return cleanup(st);
   if ((st = upload(&p->d_A, A)) != KSC_OK) return cleanup(st);
   if ((st = upload(&p->d_pre, A)) != KSC_OK) return cleanup(st);  // overwritten per dtau
   auto upload_d = [&](double** dst, const std::vector<double>& v) -> ksc_status {
@@ -502,9 +629,9 @@ ksc_status ksc_destroy(ksc_problem* p) {
   if (!p) return fail(KSC_ERR_ARG, "ksc_destroy: null problem");
   drop_graph(p);
   if (p->cap_stream) hipStreamDestroy(p->cap_stream);
-  void* bufs[] = {p->d_cd, p->d_tiles, p->d_cs,     p->d_wlT,    p->d_wlD,   p->d_q,
-                  p->d_A,  p->d_pre,   p->d_sqrtL,  p->d_part,   p->d_prevJ2, p->d_flags,
-                  p->d_J2};
+  void* bufs[] = {p->d_cd,  p->d_tiles, p->d_cs,    p->d_wlT,  p->d_wlD,    p->d_qN,
+                  p->d_qY,  p->d_A,     p->d_pre,   p->d_sqrtL, p->d_part, p->d_prevJ2,
+                  p->d_flags, p->d_J2,  p->d_edge};
   for (void* b : bufs)
     if (b) hipFree(b);
   delete p;
@@ -571,19 +698,15 @@ ksc_status ksc_spec_to_phys(ksc_problem* p, const void* state, void* phys) {
 
 ksc_status ksc_eval_J(ksc_problem* p, const void* state, double* J2, double* Jarc) {
   if (!p || !state || !J2) return fail(KSC_ERR_ARG, "ksc_eval_J: null pointer");
-  ksc_status st = launch_fused_any(p, ksc::MODE_J, state, nullptr, nullptr, nullptr, 0.0, p->stream);
-  if (st != KSC_OK) return st;
-  return finalize(p, J2, Jarc, nullptr, 0, p->stream);
+  return run(p, ksc::MODE_J, state, nullptr, nullptr, nullptr, J2, Jarc, 0, true, p->stream);
 }
 
 ksc_status ksc_eval_grad(ksc_problem* p, const void* state, void* grad, double* J2,
                          const double* scale) {
   if (!p || !state || !grad) return fail(KSC_ERR_ARG, "ksc_eval_grad: null pointer");
   if (grad == state) return fail(KSC_ERR_ARG, "ksc_eval_grad: grad must not alias state");
-  ksc_status st = launch_fused_any(p, ksc::MODE_GRAD, state, grad, scale, nullptr, 0.0, p->stream);
-  if (st != KSC_OK) return st;
-  if (J2) return finalize(p, J2, nullptr, nullptr, 0, p->stream);
-  return KSC_OK;
+  return run(p, ksc::MODE_GRAD, state, grad, scale, nullptr, J2, nullptr, 0, J2 != nullptr,
+             p->stream);
 }
 
 ksc_status ksc_step(ksc_problem* p, const void* in, void* out, double dtau, double* J2) {
@@ -592,10 +715,8 @@ ksc_status ksc_step(ksc_problem* p, const void* in, void* out, double dtau, doub
   if (!(dtau > 0) || !std::isfinite(dtau)) return fail(KSC_ERR_ARG, "ksc_step: dtau must be > 0");
   ksc_status st = ensure_pre(p, dtau, p->stream);
   if (st != KSC_OK) return st;
-  st = launch_fused_any(p, ksc::MODE_STEP, in, out, nullptr, nullptr, dtau, p->stream);
-  if (st != KSC_OK) return st;
-  if (J2) return finalize(p, J2, nullptr, nullptr, 0, p->stream);
-  return KSC_OK;
+  return run(p, ksc::MODE_STEP, in, out, nullptr, nullptr, J2, nullptr, 0, J2 != nullptr,
+             p->stream);
 }
 
 // Record `every` steps (state -> scratch -> state ...) plus per-step
@@ -609,8 +730,7 @@ static ksc_status capture_descent(ksc_problem* p, void* state, void* scratch, do
   for (int i = 0; i < every && st == KSC_OK; ++i) {
     const void* in = (i % 2 == 0) ? state : scratch;
     void* out = (i % 2 == 0) ? scratch : state;
-    st = launch_fused_any(p, ksc::MODE_STEP, in, out, nullptr, active, dtau, s);
-    if (st == KSC_OK) st = finalize(p, p->d_J2, nullptr, active, 1, s);
+    st = run(p, ksc::MODE_STEP, in, out, nullptr, active, p->d_J2, nullptr, 1, true, s);
   }
   hipGraph_t g = nullptr;
   hipError_t e = hipStreamEndCapture(s, &g);
@@ -668,9 +788,8 @@ ksc_status ksc_descend(ksc_problem* p, void* state, void* scratch, int64_t n_ste
   for (int64_t i = 0; i < rem; ++i) {
     const void* in = (i % 2 == 0) ? state : scratch;
     void* out = (i % 2 == 0) ? scratch : state;
-    st = launch_fused_any(p, ksc::MODE_STEP, in, out, nullptr, active, dtau, p->stream);
+    st = run(p, ksc::MODE_STEP, in, out, nullptr, active, p->d_J2, nullptr, 1, true, p->stream);
     if (st != KSC_OK) return st;
-    if ((st = finalize(p, p->d_J2, nullptr, active, 1, p->stream)) != KSC_OK) return st;
   }
   if (rem % 2 == 1)
     KSC_HIP(hipMemcpyAsync(state, scratch, size_t(2 * p->numel_c) * p->esize(),

@@ -4,13 +4,19 @@
 // eq. KSE_residual, cost eq. cost_function_general, adjoint Sec. V.A and
 // Appendix A, descent eq. KSE_G with the semi-implicit Euler of Sec. V.C.3).
 //
-// Work decomposition: a workgroup of 64*W lanes owns one tile of consecutive
-// s-rows of one curve; lane t computes the residual of row jr = j0 - 1 + t,
-// so the tile evaluates 64W residual rows and emits the 64W - 2 interior ones
-// (the first and last lane supply the s-halo of the adjoint's d/ds).  The
-// state rows j0-2 .. j0+64W-1 are staged once in LDS (mode-major, so that
-// lane-consecutive accesses hit consecutive banks); each HBM byte of the state
-// is read once per tile and each output byte written once.
+// Work decomposition: a workgroup of 64*W lanes owns the rows j0 .. j0+64W-1
+// of one curve, one row per lane; tiles do not overlap, so every row's
+// transforms are computed exactly once.  The state rows j0-1 .. j0+64W are
+// staged in LDS (mode-major: lane-consecutive accesses hit consecutive
+// banks) for the d/ds of the residual; the residual rows are then exchanged
+// through the same buffer for the d/ds of the adjoint.  The two rows at a
+// tile boundary lack one neighbouring residual row: their lanes store the
+// partial adjoint and their residual in a small edge workspace, and the post
+// kernel (which runs after every fused launch anyway to reduce the cost)
+// adds the missing term and writes those rows.  (Finishing them inside the
+// fused kernel by the last workgroup of a curve needs a device-scope release
+// per workgroup, i.e. an L2 write-back on every XCD holding the fresh output;
+// measured, that doubled the kernel time.)
 #pragma once
 
 #include "ksc_fft.hpp"
@@ -33,7 +39,7 @@ struct CurveDev {
 
 struct TileDev {
   int curve;
-  int j0;  // first emitted row
+  int j0;  // first row of the tile
 };
 
 template <typename T>
@@ -42,21 +48,22 @@ struct KernelArgs {
   cplx<T>* __restrict__ out;          // gradient (MODE_GRAD) or next state (MODE_STEP)
   const CurveDev* __restrict__ curves;
   const TileDev* __restrict__ tiles;
-  const T* __restrict__ cs;           // per row: g_j / (2 dsigma)
-  const T* __restrict__ wlT;          // per row: w_j L (run precision)
+  const T* __restrict__ cs;           // per row: g_j / (2 dsigma), 0 on the end rows
+  const T* __restrict__ wlT;          // per row: 2 w_j L (run precision)
   const double* __restrict__ wlD;     // per row: w_j L (FP64, cost reduction)
-  const T* __restrict__ q;            // per mode: 2 pi k / L
+  const T* __restrict__ qN;           // per mode: q_k / (4 N_x)   (nonlinear term of r)
+  const T* __restrict__ qY;           // per mode: q_k / (2 N_x)   (r_x for the adjoint)
   const T* __restrict__ A;            // per mode: q^2 - q^4
-  const T* __restrict__ pre;          // per mode: 1 / (1 + dtau A^2)   (MODE_STEP)
+  const T* __restrict__ pre;          // per mode: -dtau / (1 + dtau A^2)   (MODE_STEP)
   const double* __restrict__ scale;   // per curve gradient scale, nullable
   const unsigned char* __restrict__ active;  // per curve, nullable
   double* __restrict__ partials;      // per tile: J^2, J_arc numerator, J_arc denominator
-  T dtau;
+  cplx<T>* __restrict__ edge;         // per tile: [2 slots][partial adjoint, residual][km_max]
+  int km_max;                         // stride of the edge workspace
   int n_tiles;
   int tile_base;
 };
 
-template <typename T>
 __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll
   for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
@@ -68,9 +75,9 @@ __device__ __forceinline__ double wave_sum(double v) {
 template <int W>
 __device__ __forceinline__ void reduce_partials(double a, double b, double c, double* red,
                                                 double* dst) {
-  a = wave_sum<double>(a);
-  b = wave_sum<double>(b);
-  c = wave_sum<double>(c);
+  a = wave_sum(a);
+  b = wave_sum(b);
+  c = wave_sum(c);
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   if (lane == 0) {
     red[3 * wv + 0] = a;
@@ -92,179 +99,168 @@ __device__ __forceinline__ void reduce_partials(double a, double b, double c, do
   }
 }
 
-// LDS bytes a tile needs for KM modes.
-template <typename T, int W>
-constexpr int tile_lds_bytes(int km) {
-  return (64 * W + 2) * km * int(sizeof(cplx<T>)) + 3 * W * int(sizeof(double));
-}
-
 template <int NX, typename T, int W, int MODE>
 __device__ __forceinline__ void tile_body(const KernelArgs<T>& a, const CurveDev& cd, int c,
                                           int j0, int tile, cplx<T>* buf, double* red) {
   constexpr int KM = (NX - 1) / 3 + 1;
-  constexpr int ROWS = 64 * W;   // residual rows per tile
-  constexpr int BR = ROWS + 2;   // staged state rows
+  constexpr int ROWS = 64 * W;   // rows per tile
+  constexpr int BR = ROWS + 2;   // staged rows: j0-1 .. j0+ROWS
   const int t = threadIdx.x;
   const int n_s = cd.n_s;
   const cplx<T>* __restrict__ src = a.in + cd.off;
-  const int jr = j0 - 1 + t;
+  const int jr = j0 + t;
+  const bool inrow = jr < n_s;
 
   __syncthreads();  // the previous tile of a persistent workgroup is done with the LDS
-  // ---- stage the state rows j0-2 .. j0+ROWS-1 in LDS (mode-major) ----
-  cplx<T> X[KM];
+  // ---- stage the state rows j0-1 .. j0+ROWS (own row in registers too) ----
+  cplx<T> In[KM];
   {
-    const bool ok = (jr >= 0) && (jr < n_s);
-    const cplx<T>* row = src + (long long)(ok ? jr : 0) * KM;
+    const cplx<T>* row = src + (long long)(inrow ? jr : 0) * KM;
     sfor<KM>([&](auto Kk) {
       constexpr int k = Kk;
-      cplx<T> v = ok ? row[k] : cplx<T>{T(0), T(0)};
+      cplx<T> v = inrow ? row[k] : cplx<T>{T(0), T(0)};
       if (k == 0) v.i = T(0);
-      X[k] = v;
+      In[k] = v;
       buf[k * BR + t + 1] = v;
     });
-    if (t < 2) {
-      const int je = (t == 0) ? (j0 - 2) : (j0 - 1 + ROWS);
-      const int be = (t == 0) ? 0 : (BR - 1);
-      const bool oke = (je >= 0) && (je < n_s);
-      const cplx<T>* rowe = src + (long long)(oke ? je : 0) * KM;
-      sfor<KM>([&](auto Kk) {
-        constexpr int k = Kk;
-        cplx<T> v = oke ? rowe[k] : cplx<T>{T(0), T(0)};
-        if (k == 0) v.i = T(0);
-        buf[k * BR + be] = v;
-      });
+    for (int i = t; i < 2 * KM; i += ROWS) {
+      const int side = i >= KM, k = side ? i - KM : i;
+      const int je = side ? j0 + ROWS : j0 - 1;
+      const bool ok = (je >= 0) && (je < n_s);
+      cplx<T> v = ok ? src[(long long)je * KM + k] : cplx<T>{T(0), T(0)};
+      if (k == 0) v.i = T(0);
+      buf[k * BR + (side ? BR - 1 : 0)] = v;
     }
   }
   __syncthreads();
 
-  const T* __restrict__ qv = a.q + cd.mode_off;
-  const T* __restrict__ Av = a.A + cd.mode_off;
   const bool interior = (jr >= 1) && (jr <= n_s - 2);
-  const bool owned = interior && (t >= 1) && (t <= ROWS - 2);
   const T csj = interior ? a.cs[cd.row_off + jr] : T(0);
 
-  // ---- u = physical field of row jr; N_hat = spectrum of u^2 ----
+  // Two passes through one copy of the transform code:
+  //   pass 0: In = u_hat  -> u = c2r(u_hat), S = r2c(u * u)   -> residual
+  //   pass 1: In = (i q / (2 N_x)) r_hat -> rho = c2r(In), S = r2c(u * rho) = Q_hat
   T u[NX];
-  spec_to_phys<NX, KM, T>(X, u);
-  cplx<T> R[KM];
-  T rowR = T(0), rowD = T(0);
-  {
-    T p[NX];
-    sfor<NX>([&](auto Nn) {
-      constexpr int n = Nn;
-      p[n] = u[n] * u[n];
-    });
-    cplx<T> Nh[KM];
-    phys_to_spec<NX, KM, T>(p, Nh, T(1) / T(NX));
-    // r_hat = -g (u_{j+1} - u_{j-1}) / (2 dsigma) + A u_hat - (i q / 2) N_hat
-    sfor<KM>([&](auto Kk) {
-      constexpr int k = Kk;
-      constexpr T ck = (k == 0) ? T(1) : T(2);
-      const cplx<T> xm = buf[k * BR + t];
-      const cplx<T> xp = buf[k * BR + t + 2];
-      const T dr = xp.r - xm.r, di = xp.i - xm.i;
-      const T qh = T(0.5) * qv[k];
-      const T Ak = Av[k];
-      T rr = fmaT(-csj, dr, fmaT(Ak, X[k].r, qh * Nh[k].i));
-      T ri = fmaT(-csj, di, fmaT(Ak, X[k].i, -qh * Nh[k].r));
-      if (k == 0) ri = T(0);
-      if (!interior) {
-        rr = T(0);
-        ri = T(0);
-      }
-      R[k].r = rr;
-      R[k].i = ri;
-      rowR = fmaT(ck * rr, rr, fmaT(ck * ri, ri, rowR));
-      rowD = fmaT(ck * dr, dr, fmaT(ck * di, di, rowD));
-    });
-  }
-  {
-    double pj = 0.0, pn = 0.0, pd = 0.0;
-    if (owned) {
-      const double rR = double(rowR), rD = double(rowD);
-      pj = a.wlD[cd.row_off + jr] * rR;
-      pn = sqrt(rR * rD);
-      pd = sqrt(rD);
-    }
-    reduce_partials<W>(pj, pn, pd, red, a.partials + 3ll * tile);
-  }
-  if constexpr (MODE == MODE_J) {
-    return;
-  } else {
-    __syncthreads();  // everyone has read the staged state
-    sfor<KM>([&](auto Kk) {
-      constexpr int k = Kk;
-      buf[k * BR + t] = R[k];
-    });
-    __syncthreads();
-
-    // ---- rho = physical field of r_x; Q_hat = spectrum of u * rho ----
-    cplx<T> Q[KM];
+  cplx<T> S[KM];
+  constexpr int NPASS = (MODE == MODE_J) ? 1 : 2;
+#pragma clang loop unroll(disable)
+  for (int pass = 0; pass < NPASS; ++pass) {
     {
-      cplx<T> Y[KM];
-      sfor<KM>([&](auto Kk) {
-        constexpr int k = Kk;
-        const T qk = qv[k];
-        Y[k].r = -qk * R[k].i;
-        Y[k].i = qk * R[k].r;
-      });
-      T rho[NX];
-      spec_to_phys<NX, KM, T>(Y, rho);
+      T v[NX];
+      spec_to_phys<NX, KM, T>(In, v);
+      if (pass == 0) {
+        sfor<NX>([&](auto Nn) {
+          constexpr int n = Nn;
+          u[n] = v[n];
+        });
+      }
       sfor<NX>([&](auto Nn) {
         constexpr int n = Nn;
-        rho[n] = u[n] * rho[n];
+        v[n] = u[n] * v[n];
       });
-      phys_to_spec<NX, KM, T>(rho, Q, T(1) / T(NX));
+      phys_to_spec2<NX, KM, T>(v, S);
     }
+    if (pass == 0) {
+      // r_hat = -g (u_{j+1} - u_{j-1}) / (2 dsigma) + A u_hat - (i q / 2) N_hat
+      const T* __restrict__ qNv = a.qN + cd.mode_off;
+      const T* __restrict__ Av = a.A + cd.mode_off;
+      T rowR0 = T(0), rowR = T(0), rowD0 = T(0), rowD = T(0);
+      cplx<T> R[KM];
+      sfor<KM>([&](auto Kk) {
+        constexpr int k = Kk;
+        const cplx<T> xm = buf[k * BR + t];
+        const cplx<T> xp = buf[k * BR + t + 2];
+        const T dr = xp.r - xm.r;
+        T rr, ri;
+        if constexpr (k == 0) {
+          rr = -csj * dr;
+          ri = T(0);
+          rowR0 = rr * rr;
+          if constexpr (MODE == MODE_J) rowD0 = dr * dr;
+        } else {
+          const T di = xp.i - xm.i;
+          const T qn = qNv[k];
+          const T Ak = Av[k];
+          rr = fmaT(-csj, dr, fmaT(Ak, In[k].r, qn * S[k].i));
+          ri = fmaT(-csj, di, fmaT(Ak, In[k].i, -qn * S[k].r));
+          rowR = fmaT(rr, rr, fmaT(ri, ri, rowR));
+          if constexpr (MODE == MODE_J) rowD = fmaT(dr, dr, fmaT(di, di, rowD));
+        }
+        R[k] = interior ? cplx<T>{rr, ri} : cplx<T>{T(0), T(0)};
+      });
+      double pj = 0.0, pn = 0.0, pd = 0.0;
+      if (interior) {
+        const double rR = double(rowR0) + 2.0 * double(rowR);
+        pj = a.wlD[cd.row_off + jr] * rR;
+        if constexpr (MODE == MODE_J) {
+          const double rD = double(rowD0) + 2.0 * double(rowD);
+          pn = sqrt(rR * rD);
+          pd = sqrt(rD);
+        }
+      }
+      reduce_partials<W>(pj, pn, pd, red, a.partials + 3ll * tile);
+      if constexpr (MODE != MODE_J) {
+        // exchange residual rows through the staging buffer (outside rows read as 0)
+        __syncthreads();
+        const T* __restrict__ qYv = a.qY + cd.mode_off;
+        sfor<KM>([&](auto Kk) {
+          constexpr int k = Kk;
+          buf[k * BR + t + 1] = R[k];
+          const T qk = qYv[k];
+          In[k] = cplx<T>{-qk * R[k].i, qk * R[k].r};
+        });
+        for (int i = t; i < 2 * KM; i += ROWS) {
+          const int side = i >= KM, k = side ? i - KM : i;
+          buf[k * BR + (side ? BR - 1 : 0)] = cplx<T>{T(0), T(0)};
+        }
+        __syncthreads();
+      }
+    }
+  }
 
+  if constexpr (MODE != MODE_J) {
     // ---- L^dagger r = g (r_{j+1} - r_{j-1}) / (2 dsigma) + Q_hat + A r_hat ----
-    const int tm = (t >= 1) ? t - 1 : 0;
-    const int tp = (t <= ROWS - 2) ? t + 1 : ROWS - 1;
-    cplx<T>* __restrict__ dstrow = a.out + cd.off + (long long)jr * KM;
-    if constexpr (MODE == MODE_GRAD) {
-      const T sc = (a.scale != nullptr) ? T(a.scale[c]) : T(1);
-      const T two_wl = owned ? T(2) * a.wlT[cd.row_off + jr] * sc : T(0);
-      if (owned) {
+    const T* __restrict__ Av = a.A + cd.mode_off;
+    const bool fix_lo = interior && t == 0 && jr - 1 >= 1;
+    const bool fix_hi = interior && t == ROWS - 1 && jr + 1 <= n_s - 2;
+    cplx<T> D[KM];
+    sfor<KM>([&](auto Kk) {
+      constexpr int k = Kk;
+      const cplx<T> rm = buf[k * BR + t];
+      const cplx<T> r0 = buf[k * BR + t + 1];
+      const cplx<T> rp = buf[k * BR + t + 2];
+      const T Ak = Av[k];
+      D[k].r = fmaT(csj, rp.r - rm.r, fmaT(Ak, r0.r, S[k].r));
+      D[k].i = (k == 0) ? T(0) : fmaT(csj, rp.i - rm.i, fmaT(Ak, r0.i, S[k].i));
+    });
+    if (fix_lo || fix_hi) {
+      cplx<T>* e = a.edge + ((long long)tile * 4 + (fix_hi ? 2 : 0)) * a.km_max;
+      sfor<KM>([&](auto Kk) {
+        constexpr int k = Kk;
+        e[k] = D[k];
+        e[a.km_max + k] = buf[k * BR + t + 1];
+      });
+    } else if (inrow) {
+      cplx<T>* __restrict__ dst = a.out + cd.off + (long long)jr * KM;
+      if constexpr (MODE == MODE_GRAD) {
+        const T sc = (a.scale != nullptr) ? T(a.scale[c]) : T(1);
+        const T f0 = a.wlT[cd.row_off + jr] * sc;
         sfor<KM>([&](auto Kk) {
           constexpr int k = Kk;
           constexpr T ck = (k == 0) ? T(1) : T(2);
-          const cplx<T> rm = buf[k * BR + tm];
-          const cplx<T> rp = buf[k * BR + tp];
-          const T Ak = Av[k];
-          T gr = fmaT(csj, rp.r - rm.r, fmaT(Ak, R[k].r, Q[k].r));
-          T gi = fmaT(csj, rp.i - rm.i, fmaT(Ak, R[k].i, Q[k].i));
-          const T f = two_wl * ck;
-          cplx<T> o;
-          o.r = f * gr;
-          o.i = (k == 0) ? T(0) : f * gi;
-          dstrow[k] = o;
+          dst[k] = interior ? cplx<T>{(ck * f0) * D[k].r, (ck * f0) * D[k].i}
+                            : cplx<T>{T(0), T(0)};
         });
-      } else if ((jr == 0 || jr == n_s - 1) && jr >= 0 && jr < n_s) {
+      } else {  // MODE_STEP: u_hat - dtau L^dagger / (1 + dtau A^2); end rows copied
+        const T* __restrict__ pv = a.pre + cd.mode_off;
+        const cplx<T>* __restrict__ xrow = src + (long long)jr * KM;
         sfor<KM>([&](auto Kk) {
           constexpr int k = Kk;
-          dstrow[k] = cplx<T>{T(0), T(0)};
-        });
-      }
-    } else {  // MODE_STEP
-      const T* __restrict__ pv = a.pre + cd.mode_off;
-      if (owned) {
-        sfor<KM>([&](auto Kk) {
-          constexpr int k = Kk;
-          const cplx<T> rm = buf[k * BR + tm];
-          const cplx<T> rp = buf[k * BR + tp];
-          const T Ak = Av[k];
-          T gr = fmaT(csj, rp.r - rm.r, fmaT(Ak, R[k].r, Q[k].r));
-          T gi = fmaT(csj, rp.i - rm.i, fmaT(Ak, R[k].i, Q[k].i));
-          const T f = -a.dtau * pv[k];
-          cplx<T> o;
-          o.r = fmaT(f, gr, X[k].r);
-          o.i = (k == 0) ? T(0) : fmaT(f, gi, X[k].i);
-          dstrow[k] = o;
-        });
-      } else if ((jr == 0 || jr == n_s - 1) && jr >= 0 && jr < n_s) {
-        sfor<KM>([&](auto Kk) {
-          constexpr int k = Kk;
-          dstrow[k] = X[k];
+          const T f = pv[k];
+          cplx<T> x = xrow[k];
+          if (k == 0) x.i = T(0);
+          dst[k] = interior ? cplx<T>{fmaT(f, D[k].r, x.r), (k == 0) ? T(0) : fmaT(f, D[k].i, x.i)}
+                            : x;
         });
       }
     }
@@ -276,17 +272,13 @@ template <int NX, typename T, int W>
 __device__ __forceinline__ void tile_copy(const KernelArgs<T>& a, const CurveDev& cd, int j0,
                                           int tile, double* red) {
   constexpr int KM = (NX - 1) / 3 + 1;
-  constexpr int ROWS = 64 * W;
-  const int t = threadIdx.x;
-  const int jr = j0 - 1 + t;
-  const bool interior = (jr >= 1) && (jr <= cd.n_s - 2);
-  const bool owned = interior && (t >= 1) && (t <= ROWS - 2);
-  const bool pinned = (jr == 0 || jr == cd.n_s - 1) && jr >= 0 && jr < cd.n_s;
-  if (owned || pinned) {
+  const int jr = j0 + threadIdx.x;
+  if (jr < cd.n_s) {
     const cplx<T>* s = a.in + cd.off + (long long)jr * KM;
     cplx<T>* d = a.out + cd.off + (long long)jr * KM;
     for (int k = 0; k < KM; ++k) d[k] = s[k];
   }
+  __syncthreads();
   reduce_partials<W>(0.0, 0.0, 0.0, red, a.partials + 3ll * tile);
 }
 

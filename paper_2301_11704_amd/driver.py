@@ -1,0 +1,187 @@
+"""Descent driver: integrate du/dtau = -L^dagger(u; r) (eq. KSE_G) with the
+semi-implicit Euler step until every curve reaches a target J, the paper's
+monitor J_arc (eq. J_arc) falls below its threshold, or a step budget runs out.
+
+Policy (all decisions on the host, every `every` steps, from the J2 trace the
+library writes while the steps run as captured HIP graphs):
+  * FP32 phase until J < switch_J or J stops decreasing for `stall_records`
+    consecutive records (the FP32 rounding floor); then the state is promoted
+    to FP64 and the same kernels continue in FP64.
+  * A record in which J of a curve rose by more than rise_tol (relative) or
+    became non-finite rolls the whole batch back to the last accepted state
+    and halves dtau; smaller rises count as a stall (rounding noise).
+  * Curves that reached the target are frozen (the library's active mask), so
+    the batch keeps running for the others.
+  * Checkpoints (.npz) hold the state, dtype, tau, step count, dtau, the
+    active mask and the history; resuming continues bitwise identically
+    because the kernels are deterministic.
+
+The driver talks to a backend object (``GpuBackend`` here); any object with
+the same methods can stand in for it, which is how the failure handling is
+tested on the CPU.
+"""
+from __future__ import annotations
+
+import json
+from dataclasses import dataclass, field
+
+import numpy as np
+
+
+@dataclass
+class DescentLog:
+    steps: int = 0
+    tau: float = 0.0
+    dtau: float = 0.0
+    dtype: str = "f32"
+    J_history: list = field(default_factory=list)  # (step, [J per curve])
+    events: list = field(default_factory=list)     # (step, text)
+    converged: np.ndarray | None = None
+
+
+class GpuBackend:
+    """Backend over the HIP library (Problem) for one dtype."""
+
+    def __init__(self, problem, state):
+        self.prob = problem
+        self.state = state
+        import torch
+        self._torch = torch
+        self.scratch = torch.empty_like(state)
+        self.active = torch.ones(problem.n_curves, dtype=torch.uint8, device=state.device)
+
+    @property
+    def dtype(self) -> str:
+        return "f64" if self.state.dtype == self._torch.float64 else "f32"
+
+    def n_curves(self) -> int:
+        return self.prob.n_curves
+
+    def run(self, n_steps: int, dtau: float, every: int) -> np.ndarray:
+        tr = self.prob.descend(self.state, n_steps, dtau, every=every, scratch=self.scratch,
+                               active=self.active)
+        return tr.cpu().numpy()
+
+    def J2(self) -> np.ndarray:
+        return self.prob.eval_J(self.state).cpu().numpy()
+
+    def J_arc(self) -> np.ndarray:
+        return self.prob.eval_J(self.state, arc=True)[1].cpu().numpy()
+
+    def set_active(self, mask: np.ndarray) -> None:
+        self.active.copy_(self._torch.from_numpy(mask.astype(np.uint8)))
+
+    def snapshot(self) -> np.ndarray:
+        return self.state.detach().cpu().numpy().copy()
+
+    def restore(self, arr: np.ndarray) -> None:
+        self.state.copy_(self._torch.from_numpy(arr).to(self.state.dtype))
+
+    def promote(self) -> "GpuBackend":
+        """The same curves continued in FP64."""
+        from .problem import Problem
+        p64 = Problem(self.prob.curves, dtype=self._torch.float64, device=self.state.device)
+        b = GpuBackend(p64, self.state.double())
+        b.active.copy_(self.active)
+        return b
+
+    def flags(self) -> np.ndarray:
+        return self.prob.query_flags()
+
+
+def save_checkpoint(path: str, backend, log: DescentLog, active: np.ndarray) -> None:
+    np.savez(path, state=backend.snapshot(), dtype=log.dtype, steps=log.steps, tau=log.tau,
+             dtau=log.dtau, active=active.astype(np.uint8),
+             history=json.dumps([(s, list(map(float, j))) for s, j in log.J_history]),
+             events=json.dumps(log.events))
+
+
+def load_checkpoint(path: str):
+    d = np.load(path, allow_pickle=False)
+    log = DescentLog(steps=int(d["steps"]), tau=float(d["tau"]), dtau=float(d["dtau"]),
+                     dtype=str(d["dtype"]))
+    log.J_history = [(s, np.array(j)) for s, j in json.loads(str(d["history"]))]
+    log.events = [tuple(e) for e in json.loads(str(d["events"]))]
+    return d["state"], d["active"].astype(bool), log
+
+
+def descend_to(backend, dtau: float, J_target: float = 1e-8, max_steps: int = 10**6,
+               every: int = 100, chunk: int | None = None, switch_J: float = 1e-8,
+               stall_records: int = 10, fp64_finish: bool = True, Jarc_target: float | None = None,
+               min_dtau: float = 1e-9, rise_tol: float = 1e-3, checkpoint: str | None = None,
+               checkpoint_every: int | None = None, resume: bool = False, log: DescentLog | None = None):
+    """Run the descent; returns (backend, DescentLog).  The returned backend may
+    be a promoted (FP64) one holding the final state."""
+    every = max(1, int(every))
+    chunk = int(chunk or every)
+    chunk = max(every, (chunk // every) * every)
+    nc = backend.n_curves()
+    active = np.ones(nc, dtype=bool)
+    if log is None:
+        log = DescentLog(dtau=dtau, dtype=backend.dtype)
+    if resume and checkpoint:
+        arr, active, log = load_checkpoint(checkpoint)
+        if log.dtype == "f64" and backend.dtype != "f64":
+            backend = backend.promote()
+        backend.restore(arr)
+        dtau = log.dtau
+    backend.set_active(active)
+    last_good = backend.snapshot()
+    J_prev = np.sqrt(np.maximum(backend.J2(), 0.0))
+    best = J_prev.copy()
+    stall = np.zeros(nc, dtype=int)
+    log.converged = J_prev < J_target
+    since_ckpt = 0
+    while log.steps < max_steps:
+        n = min(chunk, max_steps - log.steps)
+        n = max(every, (n // every) * every)
+        tr = backend.run(n, dtau, every)
+        J2 = backend.J2()
+        Jn = np.sqrt(np.abs(J2))
+        # a rise beyond rounding noise (rise_tol, relative) or a non-finite cost
+        rose = (~np.isfinite(J2)) | (np.isfinite(J_prev) & (Jn > J_prev * (1 + rise_tol)) & active)
+        trace_bad = ~np.all(np.isfinite(tr[:, active]), axis=0) if tr.size else np.zeros(active.sum(), bool)
+        if np.any(rose & active) or np.any(trace_bad):
+            backend.restore(last_good)
+            dtau *= 0.5
+            log.events.append((log.steps, f"J rose or non-finite; rollback, dtau -> {dtau:.3g}"))
+            if dtau < min_dtau:
+                log.events.append((log.steps, "dtau below minimum; stopping"))
+                break
+            continue
+        log.steps += n
+        log.tau += n * dtau
+        log.dtau = dtau
+        log.J_history.append((log.steps, Jn.copy()))
+        improved = Jn < best * (1 - 1e-7)
+        stall = np.where(improved, 0, stall + 1)
+        best = np.minimum(best, Jn)
+        J_prev = Jn
+        last_good = backend.snapshot()
+        done = Jn < J_target
+        if Jarc_target is not None:
+            done = done | (backend.J_arc() < Jarc_target)
+        newly = done & active
+        if np.any(newly):
+            log.events.append((log.steps, f"converged: {np.flatnonzero(newly).tolist()}"))
+        active = active & ~done
+        log.converged = done | log.converged
+        backend.set_active(active)
+        if not np.any(active):
+            break
+        if fp64_finish and backend.dtype == "f32":
+            need = active & ((Jn < switch_J) | (stall >= stall_records))
+            if np.any(need):
+                backend = backend.promote()
+                backend.set_active(active)
+                log.dtype = "f64"
+                log.events.append((log.steps, "switched to FP64"))
+                last_good = backend.snapshot()
+                stall[:] = 0
+        since_ckpt += n
+        if checkpoint and checkpoint_every and since_ckpt >= checkpoint_every:
+            save_checkpoint(checkpoint, backend, log, active)
+            since_ckpt = 0
+    if checkpoint:
+        save_checkpoint(checkpoint, backend, log, active)
+    return backend, log
