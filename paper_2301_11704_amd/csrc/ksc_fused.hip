@@ -11,10 +11,10 @@ namespace ksc {
 
 template <int NX, typename T, int W, int MODE>
 __global__ __launch_bounds__(64 * W) void fused_kernel(KernelArgs<T> a) {
-  extern __shared__ double smem_d[];
+  extern __shared__ __align__(16) double smem_d[];
   constexpr int KM = (NX - 1) / 3 + 1;
   cplx<T>* buf = reinterpret_cast<cplx<T>*>(smem_d);
-  double* red = reinterpret_cast<double*>(buf + (64 * W + 2) * KM);
+  double* red = reinterpret_cast<double*>(buf + (64 * W + 2) * KM + 2);
   for (int i = blockIdx.x; i < a.n_tiles; i += gridDim.x) {
     const int tile = a.tile_base + i;
     const TileDev td = a.tiles[tile];
@@ -30,9 +30,9 @@ __global__ __launch_bounds__(64 * W) void fused_kernel(KernelArgs<T> a) {
 #ifdef KSC_MIXED
 template <typename T, int W, int MODE>
 __global__ __launch_bounds__(64 * W) void mixed_kernel(KernelArgs<T> a) {
-  extern __shared__ double smem_d[];
+  extern __shared__ __align__(16) double smem_d[];
   cplx<T>* buf = reinterpret_cast<cplx<T>*>(smem_d);
-  double* red = reinterpret_cast<double*>(buf + (64 * W + 2) * ((128 - 1) / 3 + 1));
+  double* red = reinterpret_cast<double*>(buf + (64 * W + 2) * ((128 - 1) / 3 + 1) + 2);
   for (int i = blockIdx.x; i < a.n_tiles; i += gridDim.x) {
     const int tile = a.tile_base + i;
     const TileDev td = a.tiles[tile];
@@ -103,7 +103,7 @@ namespace ksc {
 // not instantiated.
 template <typename T, int W, int KM>
 constexpr bool tile_fits() {
-  return (64 * W + 2) * KM * int(sizeof(cplx<T>)) + 3 * W * 8 <= 160 * 1024;
+  return ((64 * W + 2) * KM + 2) * int(sizeof(cplx<T>)) + 3 * W * 8 <= 160 * 1024;
 }
 
 #ifndef KSC_MIXED

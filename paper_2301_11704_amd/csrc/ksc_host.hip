@@ -235,7 +235,7 @@ int rows_per_tile(int W) { return 64 * W; }
 
 size_t lds_bytes(const ksc_problem* p, int W, int km) {
   const size_t cs = 2 * p->esize();
-  return size_t(64 * W + 2) * km * cs + 3 * W * sizeof(double);
+  return (size_t(64 * W + 2) * km + 2) * cs + 3 * W * sizeof(double);
 }
 
 // Largest W in {4, 2, 1} (at most `cap`) whose staging buffer fits in LDS.

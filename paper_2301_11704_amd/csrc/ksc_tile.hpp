@@ -99,42 +99,114 @@ __device__ __forceinline__ void reduce_partials(double a, double b, double c, do
   }
 }
 
+// 16-byte vector of the state type (two FP32 complex values or one FP64).
+template <typename T>
+struct alignas(16) vec16 {
+  T v[4 / (sizeof(T) / 4)];
+};
+
+// Copy the contiguous complex range [G_lo, G_hi) of global memory `g` into LDS
+// `buf`, global index G landing at buf[G - base + shift]; everything else of
+// the n elements starting at buf[0] is zero-filled.  `base - shift` is
+// 16-byte aligned, so whole 16-byte chunks move with one load and one LDS
+// store; a chunk straddling the valid range is moved element by element.
+template <typename T, int NT>
+__device__ __forceinline__ void stage_block(cplx<T>* __restrict__ buf, const cplx<T>* __restrict__ g,
+                                            long long base, int shift, int n, long long G_lo,
+                                            long long G_hi) {
+  constexpr int E = 16 / int(sizeof(cplx<T>));  // complex values per chunk
+  const long long G0 = base - shift;             // global index of buf[0]
+  const int nq = (n + E - 1) / E;
+  for (int q = threadIdx.x; q < nq; q += NT) {
+    const long long G = G0 + (long long)q * E;
+    vec16<T> w;
+    if (G >= G_lo && G + E <= G_hi) {
+      w = *reinterpret_cast<const vec16<T>*>(g + G);
+    } else {
+#pragma unroll
+      for (int h = 0; h < E; ++h) {
+        const bool ok = (G + h >= G_lo) && (G + h < G_hi);
+        const cplx<T> x = ok ? g[G + h] : cplx<T>{T(0), T(0)};
+        w.v[2 * h] = x.r;
+        w.v[2 * h + 1] = x.i;
+      }
+    }
+    reinterpret_cast<vec16<T>*>(buf)[q] = w;
+  }
+}
+
+// Write LDS rows back: global index G in [G_lo, G_hi) receives buf[G - base + shift]
+// (ADD: plus the input g_in[G], the state update of a descent step).  Chunks
+// are 16-byte aligned in both spaces; a chunk straddling the range is written
+// element by element so no row outside [G_lo, G_hi) is touched.
+template <typename T, int NT, bool ADD>
+__device__ __forceinline__ void flush_block(cplx<T>* __restrict__ gout,
+                                            const cplx<T>* __restrict__ gin,
+                                            const cplx<T>* __restrict__ buf, long long base,
+                                            int shift, int n, long long G_lo, long long G_hi) {
+  constexpr int E = 16 / int(sizeof(cplx<T>));
+  const long long G0 = base - shift;
+  const int nq = (n + E - 1) / E;
+  for (int q = threadIdx.x; q < nq; q += NT) {
+    const long long G = G0 + (long long)q * E;
+    if (G + E <= G_lo || G >= G_hi) continue;
+    vec16<T> w = reinterpret_cast<const vec16<T>*>(buf)[q];
+    if (G >= G_lo && G + E <= G_hi) {
+      if constexpr (ADD) {
+        const vec16<T> x = *reinterpret_cast<const vec16<T>*>(gin + G);
+#pragma unroll
+        for (int h = 0; h < 2 * E; ++h) w.v[h] += x.v[h];
+      }
+      *reinterpret_cast<vec16<T>*>(gout + G) = w;
+    } else {
+#pragma unroll
+      for (int h = 0; h < E; ++h) {
+        if (G + h >= G_lo && G + h < G_hi) {
+          cplx<T> y{w.v[2 * h], w.v[2 * h + 1]};
+          if constexpr (ADD) {
+            const cplx<T> x = gin[G + h];
+            y.r += x.r;
+            y.i += x.i;
+          }
+          gout[G + h] = y;
+        }
+      }
+    }
+  }
+}
+
 template <int NX, typename T, int W, int MODE>
 __device__ __forceinline__ void tile_body(const KernelArgs<T>& a, const CurveDev& cd, int c,
                                           int j0, int tile, cplx<T>* buf, double* red) {
   constexpr int KM = (NX - 1) / 3 + 1;
   constexpr int ROWS = 64 * W;   // rows per tile
   constexpr int BR = ROWS + 2;   // staged rows: j0-1 .. j0+ROWS
+  constexpr int E = 16 / int(sizeof(cplx<T>));
   const int t = threadIdx.x;
   const int n_s = cd.n_s;
-  const cplx<T>* __restrict__ src = a.in + cd.off;
   const int jr = j0 + t;
   const bool inrow = jr < n_s;
-
-  __syncthreads();  // the previous tile of a persistent workgroup is done with the LDS
-  // ---- stage the state rows j0-1 .. j0+ROWS (own row in registers too) ----
-  cplx<T> In[KM];
-  {
-    const cplx<T>* row = src + (long long)(inrow ? jr : 0) * KM;
-    sfor<KM>([&](auto Kk) {
-      constexpr int k = Kk;
-      cplx<T> v = inrow ? row[k] : cplx<T>{T(0), T(0)};
-      if (k == 0) v.i = T(0);
-      In[k] = v;
-      buf[k * BR + t + 1] = v;
-    });
-    for (int i = t; i < 2 * KM; i += ROWS) {
-      const int side = i >= KM, k = side ? i - KM : i;
-      const int je = side ? j0 + ROWS : j0 - 1;
-      const bool ok = (je >= 0) && (je < n_s);
-      cplx<T> v = ok ? src[(long long)je * KM + k] : cplx<T>{T(0), T(0)};
-      if (k == 0) v.i = T(0);
-      buf[k * BR + (side ? BR - 1 : 0)] = v;
-    }
-  }
-  __syncthreads();
-
   const bool interior = (jr >= 1) && (jr <= n_s - 2);
+
+  // LDS row-major: staged row b (= state row j0-1+b) starts at buf[sh + b*KM];
+  // sh aligns the block so that 16-byte chunks line up with global memory.
+  const long long base = cd.off + (long long)(j0 - 1) * KM;
+  const int sh = int(((base % E) + E) % E);
+  __syncthreads();  // the previous tile of a persistent workgroup is done with the LDS
+  stage_block<T, ROWS>(buf, a.in, base, sh, BR * KM + sh,
+                       cd.off + (long long)(j0 > 0 ? j0 - 1 : 0) * KM,
+                       cd.off + (long long)min(n_s, j0 + ROWS + 1) * KM);
+  __syncthreads();
+  cplx<T>* __restrict__ rows = buf + sh;
+
+  cplx<T> In[KM];
+  sfor<KM>([&](auto Kk) {
+    constexpr int k = Kk;
+    cplx<T> v = rows[(t + 1) * KM + k];
+    if (k == 0) v.i = T(0);
+    In[k] = v;
+  });
+  const T x0i = rows[(t + 1) * KM].i;  // raw Im u_hat_0 (zeroed in the output)
   const T csj = interior ? a.cs[cd.row_off + jr] : T(0);
 
   // Two passes through one copy of the transform code:
@@ -168,8 +240,8 @@ __device__ __forceinline__ void tile_body(const KernelArgs<T>& a, const CurveDev
       cplx<T> R[KM];
       sfor<KM>([&](auto Kk) {
         constexpr int k = Kk;
-        const cplx<T> xm = buf[k * BR + t];
-        const cplx<T> xp = buf[k * BR + t + 2];
+        const cplx<T> xm = rows[t * KM + k];
+        const cplx<T> xp = rows[(t + 2) * KM + k];
         const T dr = xp.r - xm.r;
         T rr, ri;
         if constexpr (k == 0) {
@@ -205,14 +277,12 @@ __device__ __forceinline__ void tile_body(const KernelArgs<T>& a, const CurveDev
         const T* __restrict__ qYv = a.qY + cd.mode_off;
         sfor<KM>([&](auto Kk) {
           constexpr int k = Kk;
-          buf[k * BR + t + 1] = R[k];
+          rows[(t + 1) * KM + k] = R[k];
           const T qk = qYv[k];
           In[k] = cplx<T>{-qk * R[k].i, qk * R[k].r};
         });
-        for (int i = t; i < 2 * KM; i += ROWS) {
-          const int side = i >= KM, k = side ? i - KM : i;
-          buf[k * BR + (side ? BR - 1 : 0)] = cplx<T>{T(0), T(0)};
-        }
+        for (int i = t; i < 2 * KM; i += ROWS)
+          rows[(i < KM) ? i : (BR - 2) * KM + i] = cplx<T>{T(0), T(0)};
         __syncthreads();
       }
     }
@@ -226,9 +296,9 @@ __device__ __forceinline__ void tile_body(const KernelArgs<T>& a, const CurveDev
     cplx<T> D[KM];
     sfor<KM>([&](auto Kk) {
       constexpr int k = Kk;
-      const cplx<T> rm = buf[k * BR + t];
-      const cplx<T> r0 = buf[k * BR + t + 1];
-      const cplx<T> rp = buf[k * BR + t + 2];
+      const cplx<T> rm = rows[t * KM + k];
+      const cplx<T> r0 = rows[(t + 1) * KM + k];
+      const cplx<T> rp = rows[(t + 2) * KM + k];
       const T Ak = Av[k];
       D[k].r = fmaT(csj, rp.r - rm.r, fmaT(Ak, r0.r, S[k].r));
       D[k].i = (k == 0) ? T(0) : fmaT(csj, rp.i - rm.i, fmaT(Ak, r0.i, S[k].i));
@@ -238,32 +308,36 @@ __device__ __forceinline__ void tile_body(const KernelArgs<T>& a, const CurveDev
       sfor<KM>([&](auto Kk) {
         constexpr int k = Kk;
         e[k] = D[k];
-        e[a.km_max + k] = buf[k * BR + t + 1];
+        e[a.km_max + k] = rows[(t + 1) * KM + k];
       });
-    } else if (inrow) {
-      cplx<T>* __restrict__ dst = a.out + cd.off + (long long)jr * KM;
-      if constexpr (MODE == MODE_GRAD) {
-        const T sc = (a.scale != nullptr) ? T(a.scale[c]) : T(1);
-        const T f0 = a.wlT[cd.row_off + jr] * sc;
-        sfor<KM>([&](auto Kk) {
-          constexpr int k = Kk;
-          constexpr T ck = (k == 0) ? T(1) : T(2);
-          dst[k] = interior ? cplx<T>{(ck * f0) * D[k].r, (ck * f0) * D[k].i}
-                            : cplx<T>{T(0), T(0)};
-        });
-      } else {  // MODE_STEP: u_hat - dtau L^dagger / (1 + dtau A^2); end rows copied
-        const T* __restrict__ pv = a.pre + cd.mode_off;
-        const cplx<T>* __restrict__ xrow = src + (long long)jr * KM;
-        sfor<KM>([&](auto Kk) {
-          constexpr int k = Kk;
-          const T f = pv[k];
-          cplx<T> x = xrow[k];
-          if (k == 0) x.i = T(0);
-          dst[k] = interior ? cplx<T>{fmaT(f, D[k].r, x.r), (k == 0) ? T(0) : fmaT(f, D[k].i, x.i)}
-                            : x;
-        });
-      }
     }
+    // ---- the tile's output rows, staged in LDS and written back coalesced ----
+    // GRAD: 2 w L c_k L^dagger (0 on the end rows);  STEP: the increment
+    // -dtau L^dagger / (1 + dtau A^2) (0 on the end rows), added to the input
+    // while writing.  The increment of Im u_hat_0 cancels its raw input value.
+    const long long obase = cd.off + (long long)j0 * KM;
+    const int osh = int(obase % E);
+    cplx<T>* __restrict__ orow = buf + osh + t * KM;
+    __syncthreads();  // every lane has read its residual neighbours
+    if constexpr (MODE == MODE_GRAD) {
+      const T sc = (a.scale != nullptr) ? T(a.scale[c]) : T(1);
+      const T f0 = interior ? a.wlT[cd.row_off + jr] * sc : T(0);
+      sfor<KM>([&](auto Kk) {
+        constexpr int k = Kk;
+        constexpr T ck = (k == 0) ? T(1) : T(2);
+        orow[k] = cplx<T>{(ck * f0) * D[k].r, (ck * f0) * D[k].i};
+      });
+    } else {
+      const T* __restrict__ pv = a.pre + cd.mode_off;
+      sfor<KM>([&](auto Kk) {
+        constexpr int k = Kk;
+        const T f = interior ? pv[k] : T(0);
+        orow[k] = cplx<T>{f * D[k].r, (k == 0) ? -x0i : f * D[k].i};
+      });
+    }
+    __syncthreads();
+    flush_block<T, ROWS, MODE == MODE_STEP>(a.out, a.in, buf, obase, osh, ROWS * KM + osh, obase,
+                                            cd.off + (long long)min(n_s, j0 + ROWS) * KM);
   }
 }
 
