@@ -14,7 +14,7 @@ __global__ __launch_bounds__(64 * W) void fused_kernel(KernelArgs<T> a) {
   extern __shared__ __align__(16) double smem_d[];
   constexpr int KM = (NX - 1) / 3 + 1;
   cplx<T>* buf = reinterpret_cast<cplx<T>*>(smem_d);
-  double* red = reinterpret_cast<double*>(buf + (64 * W + 2) * KM + 2);
+  double* red = nullptr;
   for (int i = blockIdx.x; i < a.n_tiles; i += gridDim.x) {
     const int tile = a.tile_base + i;
     const TileDev td = a.tiles[tile];
@@ -32,7 +32,7 @@ template <typename T, int W, int MODE>
 __global__ __launch_bounds__(64 * W) void mixed_kernel(KernelArgs<T> a) {
   extern __shared__ __align__(16) double smem_d[];
   cplx<T>* buf = reinterpret_cast<cplx<T>*>(smem_d);
-  double* red = reinterpret_cast<double*>(buf + (64 * W + 2) * ((128 - 1) / 3 + 1) + 2);
+  double* red = nullptr;
   for (int i = blockIdx.x; i < a.n_tiles; i += gridDim.x) {
     const int tile = a.tile_base + i;
     const TileDev td = a.tiles[tile];
@@ -103,7 +103,7 @@ namespace ksc {
 // not instantiated.
 template <typename T, int W, int KM>
 constexpr bool tile_fits() {
-  return ((64 * W + 2) * KM + 2) * int(sizeof(cplx<T>)) + 3 * W * 8 <= 160 * 1024;
+  return ((64 * W + 2) * KM + 2) * int(sizeof(cplx<T>)) <= 160 * 1024;
 }
 
 #ifndef KSC_MIXED

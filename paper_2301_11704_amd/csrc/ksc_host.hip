@@ -75,6 +75,7 @@ struct PostArgs {
   int fin_blocks;        // blocks [0, fin_blocks): one wave per curve reduces its cost
   int mode;              // MODE_GRAD / MODE_STEP: finish the tile-boundary rows
   int rows_per_tile;
+  int waves;
   int km_max;
   const cplx<T>* edge;
   const cplx<T>* in;
@@ -111,8 +112,9 @@ __global__ __launch_bounds__(256) void post_kernel(PostArgs<T> a) {
     if (a.active != nullptr && a.active[c] == 0) return;
     const CurveDev cd = a.curves[c];
     double s0 = 0, s1 = 0, s2 = 0;
-    for (int t = lane; t < cd.n_tiles; t += 64) {
-      const double* p = a.partials + 3ll * (cd.tile_begin + t);
+    const int nw = cd.n_tiles * a.waves;  // one partial triple per wave of each tile
+    for (int t = lane; t < nw; t += 64) {
+      const double* p = a.partials + 3ll * ((long long)cd.tile_begin * a.waves + t);
       s0 += p[0];
       s1 += p[1];
       s2 += p[2];
@@ -198,8 +200,6 @@ struct ksc_problem {
   void* d_cs = nullptr;
   void* d_wlT = nullptr;
   double* d_wlD = nullptr;
-  void* d_qN = nullptr;
-  void* d_qY = nullptr;
   void* d_A = nullptr;
   void* d_edge = nullptr;
   int km_max = 0;
@@ -235,7 +235,7 @@ int rows_per_tile(int W) { return 64 * W; }
 
 size_t lds_bytes(const ksc_problem* p, int W, int km) {
   const size_t cs = 2 * p->esize();
-  return (size_t(64 * W + 2) * km + 2) * cs + 3 * W * sizeof(double);
+  return (size_t(64 * W + 2) * km + 2) * cs;
 }
 
 // Largest W in {4, 2, 1} (at most `cap`) whose staging buffer fits in LDS.
@@ -276,7 +276,7 @@ ksc_status build_tiles(ksc_problem* p) {
     p->d_part = nullptr;
     p->d_edge = nullptr;
     p->part_cap = int(p->tiles.size());
-    KSC_HIP(hipMalloc(&p->d_part, 3 * sizeof(double) * p->part_cap));
+    KSC_HIP(hipMalloc(&p->d_part, 3 * 4 * sizeof(double) * p->part_cap));
     KSC_HIP(hipMalloc(&p->d_edge, size_t(p->part_cap) * 4 * p->km_max * 2 * p->esize()));
   }
   return KSC_OK;
@@ -337,9 +337,6 @@ KernelArgs<T> make_args(ksc_problem* p, const void* in, void* out, const double*
   a.cs = static_cast<const T*>(p->d_cs);
   a.wlT = static_cast<const T*>(p->d_wlT);
   a.wlD = p->d_wlD;
-  a.qN = static_cast<const T*>(p->d_qN);
-  a.qY = static_cast<const T*>(p->d_qY);
-  a.A = static_cast<const T*>(p->d_A);
   a.pre = static_cast<const T*>(p->d_pre);
   a.scale = scale;
   a.active = active;
@@ -423,6 +420,7 @@ ksc_status launch_post(ksc_problem* p, int mode, const void* in, void* out, cons
   a.fin_blocks = finalize ? (p->nc + 3) / 4 : 0;
   a.mode = mode;
   a.rows_per_tile = rows_per_tile(p->W);
+  a.waves = p->W;
   a.km_max = p->km_max;
   a.edge = static_cast<const cplx<T>*>(p->d_edge);
   a.in = static_cast<const cplx<T>*>(in);
@@ -528,7 +526,7 @@ ksc_status ksc_create(const ksc_curve_desc* descs, int32_t n_curves, int32_t dty
   p->n_cu = prop.multiProcessorCount;
 
   // layout, tables (FP64 on the host, cast to the run precision)
-  std::vector<double> cs, wl, wl2, qN, qY, A, sqrtL;
+  std::vector<double> cs, wl, wl2, A, sqrtL;
   p->cd.resize(n_curves);
   for (int c = 0; c < n_curves; ++c) {
     const ksc_curve_desc& d = descs[c];
@@ -540,6 +538,7 @@ ksc_status ksc_create(const ksc_curve_desc* descs, int32_t n_curves, int32_t dty
     cd.poff = p->phys_numel;
     cd.row_off = int(cs.size());
     cd.mode_off = int(A.size());
+    cd.q1 = 2.0 * M_PI / d.L;
     p->numel_c += (long long)d.n_s * cd.km;
     p->phys_numel += (long long)d.n_s * d.n_x;
     const double dsig = 1.0 / (d.n_s - 1);
@@ -559,9 +558,6 @@ ksc_status ksc_create(const ksc_curve_desc* descs, int32_t n_curves, int32_t dty
     }
     for (int k = 0; k < cd.km; ++k) {
       const double qk = 2.0 * M_PI * k / d.L;
-      // the r2c kernels return 2 N_x times the Fourier coefficients
-      qN.push_back(qk / (4.0 * d.n_x));
-      qY.push_back(qk / (2.0 * d.n_x));
       A.push_back(qk * qk - qk * qk * qk * qk);
     }
     sqrtL.push_back(std::sqrt(d.L));
@@ -592,8 +588,6 @@ ksc_status ksc_create(const ksc_curve_desc* descs, int32_t n_curves, int32_t dty
   ksc_status st;
   if ((st = upload(&p->d_cs, cs)) != KSC_OK) return cleanup(st);
   if ((st = upload(&p->d_wlT, wl2)) != KSC_OK) return cleanup(st);
-  if ((st = upload(&p->d_qN, qN)) != KSC_OK) return cleanup(st);
-  if ((st = upload(&p->d_qY, qY)) != KSC_OK) return cleanup(st);
   if ((st = upload(&p->d_A, A)) != KSC_OK) return cleanup(st);
   if ((st = upload(&p->d_pre, A)) != KSC_OK) return cleanup(st);  // overwritten per dtau
   auto upload_d = [&](double** dst, const std::vector<double>& v) -> ksc_status {
@@ -629,8 +623,8 @@ ksc_status ksc_destroy(ksc_problem* p) {
   if (!p) return fail(KSC_ERR_ARG, "ksc_destroy: null problem");
   drop_graph(p);
   if (p->cap_stream) hipStreamDestroy(p->cap_stream);
-  void* bufs[] = {p->d_cd,  p->d_tiles, p->d_cs,    p->d_wlT,  p->d_wlD,    p->d_qN,
-                  p->d_qY,  p->d_A,     p->d_pre,   p->d_sqrtL, p->d_part, p->d_prevJ2,
+  void* bufs[] = {p->d_cd,  p->d_tiles, p->d_cs,    p->d_wlT,    p->d_wlD,
+                  p->d_A,   p->d_pre,   p->d_sqrtL, p->d_part,   p->d_prevJ2,
                   p->d_flags, p->d_J2,  p->d_edge};
   for (void* b : bufs)
     if (b) hipFree(b);

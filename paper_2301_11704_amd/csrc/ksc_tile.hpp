@@ -35,6 +35,7 @@ struct CurveDev {
   int tile_begin;      // first tile of this curve in the tile list
   int n_tiles;
   int pad_;
+  double q1;           // 2 pi / L: q_k = k q1
 };
 
 struct TileDev {
@@ -51,51 +52,53 @@ struct KernelArgs {
   const T* __restrict__ cs;           // per row: g_j / (2 dsigma), 0 on the end rows
   const T* __restrict__ wlT;          // per row: 2 w_j L (run precision)
   const double* __restrict__ wlD;     // per row: w_j L (FP64, cost reduction)
-  const T* __restrict__ qN;           // per mode: q_k / (4 N_x)   (nonlinear term of r)
-  const T* __restrict__ qY;           // per mode: q_k / (2 N_x)   (r_x for the adjoint)
-  const T* __restrict__ A;            // per mode: q^2 - q^4
   const T* __restrict__ pre;          // per mode: -dtau / (1 + dtau A^2)   (MODE_STEP)
   const double* __restrict__ scale;   // per curve gradient scale, nullable
   const unsigned char* __restrict__ active;  // per curve, nullable
-  double* __restrict__ partials;      // per tile: J^2, J_arc numerator, J_arc denominator
+  double* __restrict__ partials;      // per tile and wave: J^2, J_arc numerator, J_arc denominator
   cplx<T>* __restrict__ edge;         // per tile: [2 slots][partial adjoint, residual][km_max]
   int km_max;                         // stride of the edge workspace
   int n_tiles;
   int tile_base;
 };
 
-__device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-  for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
+// One DPP lane move of an FP64 value (both 32-bit halves); lanes outside
+// ROW_MASK or reading an invalid source get 0.
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ double dpp_f64(double v) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_update_dpp(0, int(b), CTRL, ROW_MASK, 0xf, true);
+  const int hi = __builtin_amdgcn_update_dpp(0, int(b >> 32), CTRL, ROW_MASK, 0xf, true);
+  return __longlong_as_double((long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo));
+}
+
+// Sum over the 64 lanes of a wave with a fixed DPP pattern (inclusive scan
+// within 16-lane rows, then row broadcasts); lane 63 ends with the total.
+// The order of the additions is fixed, so the result is deterministic.
+__device__ __forceinline__ double wave_sum_to_lane63(double v) {
+  v += dpp_f64<0x111, 0xf>(v);  // row_shr:1
+  v += dpp_f64<0x112, 0xf>(v);  // row_shr:2
+  v += dpp_f64<0x114, 0xf>(v);  // row_shr:4
+  v += dpp_f64<0x118, 0xf>(v);  // row_shr:8
+  v += dpp_f64<0x142, 0xa>(v);  // row_bcast:15 into rows 1 and 3
+  v += dpp_f64<0x143, 0xc>(v);  // row_bcast:31 into rows 2 and 3
   return v;
 }
 
-// Sum three per-lane FP64 values over the workgroup in a fixed order and
-// store them as the tile's partials.
-template <int W>
-__device__ __forceinline__ void reduce_partials(double a, double b, double c, double* red,
-                                                double* dst) {
-  a = wave_sum(a);
-  b = wave_sum(b);
-  c = wave_sum(c);
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  if (lane == 0) {
-    red[3 * wv + 0] = a;
-    red[3 * wv + 1] = b;
-    red[3 * wv + 2] = c;
+// Each wave stores its partial sums (J^2, J_arc numerator, denominator) of
+// the tile; the post kernel adds them in a fixed order.
+template <int W, int NV>
+__device__ __forceinline__ void store_wave_partials(double a, double b, double c, double* dst) {
+  a = wave_sum_to_lane63(a);
+  if constexpr (NV > 1) {
+    b = wave_sum_to_lane63(b);
+    c = wave_sum_to_lane63(c);
   }
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    double s0 = 0, s1 = 0, s2 = 0;
-#pragma unroll
-    for (int w = 0; w < W; ++w) {
-      s0 += red[3 * w + 0];
-      s1 += red[3 * w + 1];
-      s2 += red[3 * w + 2];
-    }
-    dst[0] = s0;
-    dst[1] = s1;
-    dst[2] = s2;
+  if ((threadIdx.x & 63) == 63) {
+    double* d = dst + 3 * (threadIdx.x >> 6);
+    d[0] = a;
+    d[1] = (NV > 1) ? b : 0.0;
+    d[2] = (NV > 1) ? c : 0.0;
   }
 }
 
@@ -110,28 +113,35 @@ struct alignas(16) vec16 {
 // the n elements starting at buf[0] is zero-filled.  `base - shift` is
 // 16-byte aligned, so whole 16-byte chunks move with one load and one LDS
 // store; a chunk straddling the valid range is moved element by element.
-template <typename T, int NT>
+template <typename T, int NT, int NMAX>
 __device__ __forceinline__ void stage_block(cplx<T>* __restrict__ buf, const cplx<T>* __restrict__ g,
                                             long long base, int shift, int n, long long G_lo,
                                             long long G_hi) {
   constexpr int E = 16 / int(sizeof(cplx<T>));  // complex values per chunk
+  constexpr int NQ = (NMAX + E * NT - 1) / (E * NT);  // chunks per thread, at most
   const long long G0 = base - shift;             // global index of buf[0]
   const int nq = (n + E - 1) / E;
-  for (int q = threadIdx.x; q < nq; q += NT) {
+  vec16<T> w[NQ];
+#pragma unroll
+  for (int i = 0; i < NQ; ++i) {  // every load in flight before the first LDS store
+    const int q = threadIdx.x + i * NT;
     const long long G = G0 + (long long)q * E;
-    vec16<T> w;
-    if (G >= G_lo && G + E <= G_hi) {
-      w = *reinterpret_cast<const vec16<T>*>(g + G);
+    if (q < nq && G >= G_lo && G + E <= G_hi) {
+      w[i] = *reinterpret_cast<const vec16<T>*>(g + G);
     } else {
 #pragma unroll
       for (int h = 0; h < E; ++h) {
-        const bool ok = (G + h >= G_lo) && (G + h < G_hi);
+        const bool ok = q < nq && (G + h >= G_lo) && (G + h < G_hi);
         const cplx<T> x = ok ? g[G + h] : cplx<T>{T(0), T(0)};
-        w.v[2 * h] = x.r;
-        w.v[2 * h + 1] = x.i;
+        w[i].v[2 * h] = x.r;
+        w[i].v[2 * h + 1] = x.i;
       }
     }
-    reinterpret_cast<vec16<T>*>(buf)[q] = w;
+  }
+#pragma unroll
+  for (int i = 0; i < NQ; ++i) {
+    const int q = threadIdx.x + i * NT;
+    if (q < nq) reinterpret_cast<vec16<T>*>(buf)[q] = w[i];
   }
 }
 
@@ -193,12 +203,21 @@ __device__ __forceinline__ void tile_body(const KernelArgs<T>& a, const CurveDev
   const long long base = cd.off + (long long)(j0 - 1) * KM;
   const int sh = int(((base % E) + E) % E);
   __syncthreads();  // the previous tile of a persistent workgroup is done with the LDS
-  stage_block<T, ROWS>(buf, a.in, base, sh, BR * KM + sh,
+  stage_block<T, ROWS, BR * KM + E>(buf, a.in, base, sh, BR * KM + sh,
                        cd.off + (long long)(j0 > 0 ? j0 - 1 : 0) * KM,
                        cd.off + (long long)min(n_s, j0 + ROWS + 1) * KM);
   __syncthreads();
   cplx<T>* __restrict__ rows = buf + sh;
 
+  const T x0i = rows[(t + 1) * KM].i;  // raw Im u_hat_0 (zeroed in the output)
+  const T csj = interior ? a.cs[cd.row_off + jr] : T(0);
+  const T q1s = T(cd.q1 * cd.q1);                  // q1^2:  q_k^2 = k^2 q1^2
+  const T qN1 = T(cd.q1 / (4.0 * NX));             // q1 / (4 N_x): S is 2 N_x N_hat
+  const T qY1 = T(cd.q1 / (2.0 * NX));             // q1 / (2 N_x): Q_hat = r2c/(2 N_x)
+
+  // Two passes through one copy of the transform code:
+  //   pass 0: In = u_hat  -> u = c2r(u_hat), S = r2c(u * u)   -> residual
+  //   pass 1: In = (i q / (2 N_x)) r_hat -> rho = c2r(In), S = r2c(u * rho) = Q_hat
   cplx<T> In[KM];
   sfor<KM>([&](auto Kk) {
     constexpr int k = Kk;
@@ -206,15 +225,11 @@ __device__ __forceinline__ void tile_body(const KernelArgs<T>& a, const CurveDev
     if (k == 0) v.i = T(0);
     In[k] = v;
   });
-  const T x0i = rows[(t + 1) * KM].i;  // raw Im u_hat_0 (zeroed in the output)
-  const T csj = interior ? a.cs[cd.row_off + jr] : T(0);
-
-  // Two passes through one copy of the transform code:
-  //   pass 0: In = u_hat  -> u = c2r(u_hat), S = r2c(u * u)   -> residual
-  //   pass 1: In = (i q / (2 N_x)) r_hat -> rho = c2r(In), S = r2c(u * rho) = Q_hat
   T u[NX];
   cplx<T> S[KM];
   constexpr int NPASS = (MODE == MODE_J) ? 1 : 2;
+  constexpr int CH = 7;                            // modes per LDS read batch
+  constexpr int NCH = (KM + CH - 1) / CH;
 #pragma clang loop unroll(disable)
   for (int pass = 0; pass < NPASS; ++pass) {
     {
@@ -233,32 +248,52 @@ __device__ __forceinline__ void tile_body(const KernelArgs<T>& a, const CurveDev
       phys_to_spec2<NX, KM, T>(v, S);
     }
     if (pass == 0) {
-      // r_hat = -g (u_{j+1} - u_{j-1}) / (2 dsigma) + A u_hat - (i q / 2) N_hat
-      const T* __restrict__ qNv = a.qN + cd.mode_off;
-      const T* __restrict__ Av = a.A + cd.mode_off;
+      // r_hat = -g (u_{j+1} - u_{j-1}) / (2 dsigma) + A u_hat - (i q / 2) N_hat,  S = 2 N_x N_hat;
+      // the state rows are read from LDS in batches of CH modes (all reads of a
+      // batch issued before its arithmetic), keeping few values live.
       T rowR0 = T(0), rowR = T(0), rowD0 = T(0), rowD = T(0);
       cplx<T> R[KM];
-      sfor<KM>([&](auto Kk) {
-        constexpr int k = Kk;
-        const cplx<T> xm = rows[t * KM + k];
-        const cplx<T> xp = rows[(t + 2) * KM + k];
-        const T dr = xp.r - xm.r;
-        T rr, ri;
-        if constexpr (k == 0) {
-          rr = -csj * dr;
-          ri = T(0);
-          rowR0 = rr * rr;
-          if constexpr (MODE == MODE_J) rowD0 = dr * dr;
-        } else {
-          const T di = xp.i - xm.i;
-          const T qn = qNv[k];
-          const T Ak = Av[k];
-          rr = fmaT(-csj, dr, fmaT(Ak, In[k].r, qn * S[k].i));
-          ri = fmaT(-csj, di, fmaT(Ak, In[k].i, -qn * S[k].r));
-          rowR = fmaT(rr, rr, fmaT(ri, ri, rowR));
-          if constexpr (MODE == MODE_J) rowD = fmaT(dr, dr, fmaT(di, di, rowD));
-        }
-        R[k] = interior ? cplx<T>{rr, ri} : cplx<T>{T(0), T(0)};
+      // (the empty asm keeps the per-mode constants below from being hoisted out
+      // of the pass loop, where they would stay live across both transforms)
+      T q1s_r = q1s, qN1_r = qN1;
+      __asm__ volatile("" : "+v"(q1s_r), "+v"(qN1_r));
+      sfor<NCH>([&](auto Cc) {
+        constexpr int k0 = int(Cc) * CH;
+        cplx<T> xm[CH], x0[CH], xp[CH];
+        sfor<CH>([&](auto Ii) {
+          constexpr int k = k0 + int(Ii);
+          if constexpr (k < KM) {
+            xm[Ii] = rows[t * KM + k];
+            x0[Ii] = rows[(t + 1) * KM + k];
+            xp[Ii] = rows[(t + 2) * KM + k];
+          }
+        });
+        __builtin_amdgcn_sched_barrier(0);
+        sfor<CH>([&](auto Ii) {
+          constexpr int i = Ii;
+          constexpr int k = k0 + i;
+          if constexpr (k < KM) {
+            const T dr = xp[i].r - xm[i].r;
+            T rr, ri;
+            if constexpr (k == 0) {
+              rr = -csj * dr;
+              ri = T(0);
+              rowR0 = rr * rr;
+              if constexpr (MODE == MODE_J) rowD0 = dr * dr;
+            } else {
+              const T di = xp[i].i - xm[i].i;
+              const T qn = T(k) * qN1_r;
+              const T q2 = T(k * k) * q1s_r;
+              const T Ak = fmaT(-q2, q2, q2);
+              rr = fmaT(-csj, dr, fmaT(Ak, x0[i].r, qn * S[k].i));
+              ri = fmaT(-csj, di, fmaT(Ak, x0[i].i, -qn * S[k].r));
+              rowR = fmaT(rr, rr, fmaT(ri, ri, rowR));
+              if constexpr (MODE == MODE_J) rowD = fmaT(dr, dr, fmaT(di, di, rowD));
+            }
+            R[k] = interior ? cplx<T>{rr, ri} : cplx<T>{T(0), T(0)};
+          }
+        });
+        __builtin_amdgcn_sched_barrier(0);
       });
       double pj = 0.0, pn = 0.0, pd = 0.0;
       if (interior) {
@@ -270,15 +305,16 @@ __device__ __forceinline__ void tile_body(const KernelArgs<T>& a, const CurveDev
           pd = sqrt(rD);
         }
       }
-      reduce_partials<W>(pj, pn, pd, red, a.partials + 3ll * tile);
+      store_wave_partials<W, (MODE == MODE_J) ? 3 : 1>(pj, pn, pd, a.partials + 3ll * W * tile);
       if constexpr (MODE != MODE_J) {
         // exchange residual rows through the staging buffer (outside rows read as 0)
         __syncthreads();
-        const T* __restrict__ qYv = a.qY + cd.mode_off;
+        T qY1_r = qY1;
+        __asm__ volatile("" : "+v"(qY1_r));
         sfor<KM>([&](auto Kk) {
           constexpr int k = Kk;
           rows[(t + 1) * KM + k] = R[k];
-          const T qk = qYv[k];
+          const T qk = T(k) * qY1_r;
           In[k] = cplx<T>{-qk * R[k].i, qk * R[k].r};
         });
         for (int i = t; i < 2 * KM; i += ROWS)
@@ -290,18 +326,34 @@ __device__ __forceinline__ void tile_body(const KernelArgs<T>& a, const CurveDev
 
   if constexpr (MODE != MODE_J) {
     // ---- L^dagger r = g (r_{j+1} - r_{j-1}) / (2 dsigma) + Q_hat + A r_hat ----
-    const T* __restrict__ Av = a.A + cd.mode_off;
     const bool fix_lo = interior && t == 0 && jr - 1 >= 1;
     const bool fix_hi = interior && t == ROWS - 1 && jr + 1 <= n_s - 2;
     cplx<T> D[KM];
-    sfor<KM>([&](auto Kk) {
-      constexpr int k = Kk;
-      const cplx<T> rm = rows[t * KM + k];
-      const cplx<T> r0 = rows[(t + 1) * KM + k];
-      const cplx<T> rp = rows[(t + 2) * KM + k];
-      const T Ak = Av[k];
-      D[k].r = fmaT(csj, rp.r - rm.r, fmaT(Ak, r0.r, S[k].r));
-      D[k].i = (k == 0) ? T(0) : fmaT(csj, rp.i - rm.i, fmaT(Ak, r0.i, S[k].i));
+    T q1s_d = q1s;
+    __asm__ volatile("" : "+v"(q1s_d));
+    sfor<NCH>([&](auto Cc) {
+      constexpr int k0 = int(Cc) * CH;
+      cplx<T> rm[CH], r0[CH], rp[CH];
+      sfor<CH>([&](auto Ii) {
+        constexpr int k = k0 + int(Ii);
+        if constexpr (k < KM) {
+          rm[Ii] = rows[t * KM + k];
+          r0[Ii] = rows[(t + 1) * KM + k];
+          rp[Ii] = rows[(t + 2) * KM + k];
+        }
+      });
+      __builtin_amdgcn_sched_barrier(0);
+      sfor<CH>([&](auto Ii) {
+        constexpr int i = Ii;
+        constexpr int k = k0 + i;
+        if constexpr (k < KM) {
+          const T q2 = T(k * k) * q1s_d;
+          const T Ak = fmaT(-q2, q2, q2);
+          D[k].r = fmaT(csj, rp[i].r - rm[i].r, fmaT(Ak, r0[i].r, S[k].r));
+          D[k].i = (k == 0) ? T(0) : fmaT(csj, rp[i].i - rm[i].i, fmaT(Ak, r0[i].i, S[k].i));
+        }
+      });
+      __builtin_amdgcn_sched_barrier(0);
     });
     if (fix_lo || fix_hi) {
       cplx<T>* e = a.edge + ((long long)tile * 4 + (fix_hi ? 2 : 0)) * a.km_max;
@@ -329,9 +381,10 @@ __device__ __forceinline__ void tile_body(const KernelArgs<T>& a, const CurveDev
       });
     } else {
       const T* __restrict__ pv = a.pre + cd.mode_off;
+      const T m = interior ? T(1) : T(0);
       sfor<KM>([&](auto Kk) {
         constexpr int k = Kk;
-        const T f = interior ? pv[k] : T(0);
+        const T f = m * pv[k];
         orow[k] = cplx<T>{f * D[k].r, (k == 0) ? -x0i : f * D[k].i};
       });
     }
@@ -352,8 +405,7 @@ __device__ __forceinline__ void tile_copy(const KernelArgs<T>& a, const CurveDev
     cplx<T>* d = a.out + cd.off + (long long)jr * KM;
     for (int k = 0; k < KM; ++k) d[k] = s[k];
   }
-  __syncthreads();
-  reduce_partials<W>(0.0, 0.0, 0.0, red, a.partials + 3ll * tile);
+  store_wave_partials<W, 1>(0.0, 0.0, 0.0, a.partials + 3ll * W * tile);
 }
 
 }  // namespace ksc
