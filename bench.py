@@ -2,15 +2,20 @@
 on one MI355X.
 
 A step is one evaluation of J^2 and its adjoint gradient for every curve of
-the batch (the fused tile kernel plus the FP64 per-curve finalization).
-Workload (default): 64 curves, L = 66, N_x = 128 (43 kept modes), N_s = 1024,
-finite map T = 20, FP32 with FP64 cost reduction; endpoints are stored
-KS-trajectory states, the interior is the blend plus a seeded perturbation.
+the batch (the fused tile kernel plus the post kernel that finishes the tile
+boundary rows and the FP64 per-curve cost).  Workload (default): 64 curves,
+L = 66, N_x = 128 (43 kept modes), N_s = 1024, finite map T = 20, FP32 with
+FP64 cost reduction; endpoints are stored KS-trajectory states, the interior
+is the blend plus a seeded perturbation.  --workload c1/c2/c3 selects the
+single-curve and uneven-batch shapes, --dtype f64 the FP64 finish.
 
-Prints one JSON line.  value = curve-point evals/s = sum_c (N_s - 2) * steps / s.
-Also reported: the plain policy (one launch per curve), the streaming
-roofline (the batch replicated past the caches), and the FP64 oracle timed on
-the host on a bounded sample.
+Prints one JSON line.  value = curve-point evals/s = sum_c (N_s - 2) * steps / s
+over K timed steps; the roofline block uses the fused kernel's own duration
+from HIP events recorded by the library around each launch (a second window
+of K steps).  Extra legs: the plain policy (one launch per curve), the fused
+descent step, the captured-graph descent loop, autograd forward+backward, the
+streaming roofline (the batch replicated past the 256 MB last-level cache) and
+the FP64 oracle timed on the host on a bounded sample.
 """
 from __future__ import annotations
 
@@ -27,6 +32,41 @@ sys.path.insert(0, ROOT)
 
 METRIC = "curve-point gradient evals/s (J+∇J) & % HBM roofline, batched vs plain"
 HBM_PEAK_GBS = 8000.0
+# Sources of the fused tile kernel; a traffic summary under profiles/ applies
+# only while their hash is the one recorded there.
+KERNEL_SOURCES = ("ksc_tile.hpp", "ksc_fft.hpp", "ksc_fused.hip", "ksc_launch.hpp")
+STREAM_REPLICAS = {"c4": 48, "c2": 191, "c3": 20, "c1": 0}
+DTAU = {"c4": 5e-4, "c2": 1e-4, "c3": 1e-3, "c1": 1e-3}
+
+
+def kernel_source_hash() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_2301_11704_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def recorded_traffic(workload: str, dtype: str):
+    """HBM bytes per launch of the fused J+gradient kernel from the committed
+    rocprofv3 counter summary, or None if there is none or the kernel sources
+    changed since it was taken."""
+    path = os.path.join(ROOT, "profiles", f"fused_grad_{workload}_{dtype}_traffic.md")
+    if not os.path.exists(path):
+        return None
+    kv = {}
+    with open(path) as fh:
+        for line in fh:
+            if line.startswith("- ") and ": " in line:
+                k, v = line[2:].split(": ", 1)
+                kv[k.strip()] = v.strip().strip("`")
+    if kv.get("kernel_source_sha256") != kernel_source_hash():
+        return None
+    try:
+        return float(kv["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
 
 
 def _specs_and_states(workload: str):
@@ -107,7 +147,9 @@ def main():
     ap.add_argument("--workload", default="c4", choices=["c4", "c1", "c2", "c3"])
     ap.add_argument("--no-cpu", action="store_true", help="skip the host oracle baseline")
     ap.add_argument("--no-extras", action="store_true", help="skip plain and streaming legs")
-    ap.add_argument("--replicas", type=int, default=48, help="streaming-leg replication factor")
+    ap.add_argument("--dtype", default="f32", choices=["f32", "f64"])
+    ap.add_argument("--replicas", type=int, default=None,
+                    help="streaming-leg replication factor (default per workload)")
     ap.add_argument("--copy-probe", type=float, default=0.0, metavar="GB",
                     help="only run one plain device-to-device copy of this many GB (calibrates "
                          "the HBM byte counters) and exit")
@@ -132,14 +174,15 @@ def main():
 
     import paper_2301_11704_amd as ksc
     stream = torch.cuda.current_stream()
+    tdt = torch.float64 if args.dtype == "f64" else torch.float32
+    esz = 8 if args.dtype == "f64" else 4
     specs, Us, _ = _specs_and_states(args.workload)
     descs = [ksc.CurveDesc(s.n_s, s.n_x, s.L, s.map, s.scale, s.s0) for s in specs]
-    prob = ksc.Problem(descs, dtype=torch.float32)
+    prob = ksc.Problem(descs, dtype=tdt)
     X = prob.new_state()
     for c, U in enumerate(Us):
         prob.upload(X, c, U)
     G = torch.empty_like(X)
-    J2 = torch.empty(len(specs), dtype=torch.float64, device="cuda")
     prob.tune(None)
     policy, waves = prob.launch
 
@@ -150,15 +193,23 @@ def main():
         step()
     torch.cuda.synchronize()
     ms = _time(torch, step, args.steps, stream)
-    # the dominant kernel alone (no per-curve finalization)
-    ms_kernel = _time(torch, lambda: prob.eval_grad(X, G, want_J2=False), args.steps, stream)
+    # the same K evaluations again with HIP events around each kernel (on the
+    # stream the library launches on): the dominant kernel's own duration
+    prob.set_timing(True)
+    ms_ev = _time(torch, step, args.steps, stream)
+    fused_ms, post_ms, n_ev = prob.read_timing()
+    prob.set_timing(False)
+    kernel_ms = fused_ms / n_ev
+    post_kernel_ms = post_ms / n_ev
 
     info = _describe(args.workload, specs)
     pts = info["curve_points"]
     value = pts / (ms * 1e-3)
     km_rows = sum(s.n_s * ((s.n_x - 1) // 3 + 1) for s in specs)
-    alg_bytes = 16.0 * km_rows  # read + write 8 B per kept mode per row (FP32)
-    achieved = alg_bytes / (ms_kernel * 1e-3) / 1e9
+    row_bytes = 2 * esz  # one complex value per kept mode and row
+    alg_bytes = 2.0 * row_bytes * km_rows  # read the state, write the gradient
+    achieved = alg_bytes / (kernel_ms * 1e-3) / 1e9
+    traffic = recorded_traffic(args.workload, args.dtype)
 
     out = {
         "metric": METRIC,
@@ -171,39 +222,76 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32",
+        "dtype": args.dtype,
         "data": "synthetic",
         "config": dict(info, launch={"policy": policy, "waves_per_tile": waves}),
         "roofline": {
             "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-            "kernel": "fused J+grad tile kernel", "kernel_ms": ms_kernel,
+            "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+            "kernel": "fused J+gradient tile kernel", "kernel_ms": kernel_ms,
+            "post_kernel_ms": post_kernel_ms, "ms_per_step_with_events": ms_ev,
             "alg_bytes_per_launch": alg_bytes,
+            "grid_point_evals_per_s": sum((s.n_s - 2) * s.n_x for s in specs) / (ms * 1e-3),
         },
     }
 
     if not args.no_extras:
+        # plain: one non-persistent launch per curve and step
         prob.set_launch(ksc.KSC_LAUNCH_PLAIN, waves)
         ms_plain = _time(torch, step, max(10, args.steps // 4), stream)
         prob.set_launch(policy, waves)
         out["plain"] = {"value": pts / (ms_plain * 1e-3), "ms_per_step": ms_plain,
                         "speedup_batched_vs_plain": ms_plain / ms}
-        if args.workload == "c4" and args.replicas > 1:
-            big = [d for _ in range(args.replicas) for d in descs]
-            pb = ksc.Problem(big, dtype=torch.float32)
-            Xb = X.repeat(args.replicas)
+        # the fused descent step (state -> scratch), eager launches
+        Y = X.clone()
+        dtau = DTAU[args.workload]
+        ms_step = _time(torch, lambda: prob.step(X, Y, dtau), args.steps, stream)
+        out["step"] = {"ms_per_step": ms_step, "curve_points_per_s": pts / (ms_step * 1e-3),
+                       "alg_GBs": alg_bytes / (ms_step * 1e-3) / 1e9}
+        # descent loop as captured HIP graphs (100 steps per graph)
+        Z = X.clone()
+        prob.descend(Z, 200, dtau, every=100, scratch=Y)
+        nd = 100 * max(2, args.steps // 50)
+        ms_d = _time(torch, lambda: prob.descend(Z, nd, dtau, every=100, scratch=Y), 1, stream)
+        out["descend_graph"] = {"steps": nd, "ms_per_step": ms_d / nd,
+                                "curve_points_per_s": pts * nd / (ms_d * 1e-3)}
+        del Z
+        # autograd forward (J only) + backward (recomputing adjoint)
+        Xr = X.clone().requires_grad_(True)
+
+        def fwd_bwd():
+            Xr.grad = None
+            ksc.curve_J2(Xr, prob).sum().backward()
+
+        for _ in range(3):
+            fwd_bwd()
+        ms_ag = _time(torch, fwd_bwd, max(10, args.steps // 4), stream)
+        out["autograd"] = {"ms_per_step": ms_ag, "curve_points_per_s": pts / (ms_ag * 1e-3),
+                           "GBs_vs_method_minimum": alg_bytes / (ms_ag * 1e-3) / 1e9,
+                           "GBs_vs_recompute_design": 1.5 * alg_bytes / (ms_ag * 1e-3) / 1e9}
+        del Xr, Y
+        reps = STREAM_REPLICAS[args.workload] if args.replicas is None else args.replicas
+        if reps > 1:
+            # the batch replicated past the caches (MALL is 256 MB)
+            big = [d for _ in range(reps) for d in descs]
+            pb = ksc.Problem(big, dtype=tdt)
+            Xb = X.repeat(reps)
             Gb = torch.empty_like(Xb)
             pb.set_launch(policy, waves)
             for _ in range(3):
                 pb.eval_grad(Xb, Gb, want_J2=False)
-            msb = _time(torch, lambda: pb.eval_grad(Xb, Gb, want_J2=False),
-                        max(5, args.steps // 10), stream)
-            bb = alg_bytes * args.replicas
+            nb = max(5, args.steps // 10)
+            pb.set_timing(True)
+            msb = _time(torch, lambda: pb.eval_grad(Xb, Gb), nb, stream)
+            fb, _, nbe = pb.read_timing()
+            pb.set_timing(False)
+            kb = fb / nbe
+            bb = alg_bytes * reps
             out["streaming"] = {
-                "replicas": args.replicas, "state_GB": Xb.numel() * 4 / 1e9, "kernel_ms": msb,
-                "achieved_GBs": bb / (msb * 1e-3) / 1e9,
-                "frac_hbm": bb / (msb * 1e-3) / 1e9 / HBM_PEAK_GBS,
-                "curve_points_per_s": pts * args.replicas / (msb * 1e-3),
+                "replicas": reps, "state_GB": Xb.numel() * esz / 1e9, "ms_per_step": msb,
+                "kernel_ms": kb, "achieved_GBs": bb / (kb * 1e-3) / 1e9,
+                "frac_hbm": bb / (kb * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                "curve_points_per_s": pts * reps / (msb * 1e-3),
             }
             del Xb, Gb, pb
 

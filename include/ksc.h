@@ -173,6 +173,21 @@ ksc_status ksc_get_launch(const ksc_problem* p, int32_t* policy, int32_t* waves)
  * them.  Synchronizes the problem's stream. */
 ksc_status ksc_query_flags(ksc_problem* p, uint32_t* flags_host);
 
+/* Kernel timing for measurement.  enable != 0 starts a new timing window:
+ * every later ksc_eval_J / ksc_eval_grad / ksc_step call on the problem's own
+ * stream has its kernel dispatches stamp HIP events (hipExtLaunchKernelGGL
+ * start/stop events): the start and end of the fused tile kernel(s) and of
+ * the post kernel.
+ * Calls made under stream capture and ksc_descend's graphs are not timed.
+ * enable == 0 stops recording (the window keeps what it holds).  At most
+ * 65536 evaluations per window; later ones are not timed and
+ * ksc_read_timing reports KSC_ERR_STATE. */
+ksc_status ksc_set_timing(ksc_problem* p, int32_t enable);
+/* Totals over the current window: milliseconds in the fused tile kernel(s),
+ * milliseconds in the post kernel, and the number of timed evaluations.
+ * Waits for the recorded events (blocks the host). */
+ksc_status ksc_read_timing(ksc_problem* p, double* fused_ms, double* post_ms, int64_t* n_evals);
+
 /* Message of the last failed call on this thread ("" if none). */
 const char* ksc_last_error(void);
 

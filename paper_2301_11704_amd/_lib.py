@@ -24,7 +24,7 @@ EXPORTED = (
     "ksc_phys_numel", "ksc_phys_offset", "ksc_n_modes", "ksc_set_endpoints",
     "ksc_phys_to_spec", "ksc_spec_to_phys", "ksc_eval_J", "ksc_eval_grad", "ksc_step",
     "ksc_descend", "ksc_tune", "ksc_set_launch", "ksc_get_launch", "ksc_query_flags",
-    "ksc_last_error",
+    "ksc_set_timing", "ksc_read_timing", "ksc_last_error",
 )
 
 
@@ -79,6 +79,9 @@ def lib() -> ctypes.CDLL:
         "ksc_set_launch": (i32, [vp, i32, i32]),
         "ksc_get_launch": (i32, [vp, ctypes.POINTER(i32), ctypes.POINTER(i32)]),
         "ksc_query_flags": (i32, [vp, ctypes.POINTER(ctypes.c_uint32)]),
+        "ksc_set_timing": (i32, [vp, i32]),
+        "ksc_read_timing": (i32, [vp, ctypes.POINTER(dbl), ctypes.POINTER(dbl),
+                                  ctypes.POINTER(i64)]),
         "ksc_last_error": (ctypes.c_char_p, []),
     }
     for name, (res, args) in sig.items():

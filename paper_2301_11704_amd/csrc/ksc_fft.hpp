@@ -247,4 +247,148 @@ __device__ __forceinline__ void phys_to_spec(const T (&x)[N], cplx<T> (&X)[KM]) 
   });
 }
 
+// ---------------------------------------------------------------------------
+// Lane pairs: two neighbouring lanes (p = lane & 1) share one row, for grids
+// whose whole-row transform would not fit one lane's registers.
+//
+// Spectrum side, lane p holds X_k for k = 2i + p, i = 0..KH-1 (entries with
+// k > K are zero).  Physical side, lane p holds the samples x_n with
+// n in [p N/2, (p+1) N/2).
+//
+// With M = N/2 (half-length trick) and Q = M/2, the complex M-point DFT splits
+// as z_{m1 + Q m2} = sum_{k2} (-1)^{m2 k2} w_M^{m1 k2} sum_{k1} w_Q^{m1 k1}
+// Z_{2 k1 + k2}: each lane runs a Q-point FFT over its decimated spectrum, a
+// lane-dependent twiddle, and one radix-2 stage across the pair (a DPP lane
+// swap).  The forward transform runs the same steps in reverse order.
+// ---------------------------------------------------------------------------
+
+// Value of the other lane of the pair (DPP quad_perm [1, 0, 3, 2]).
+__device__ __forceinline__ float pair_swap(float v) {
+  return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0xB1, 0xf, 0xf, false));
+}
+__device__ __forceinline__ double pair_swap(double v) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_mov_dpp(int(b), 0xB1, 0xf, 0xf, false);
+  const int hi = __builtin_amdgcn_mov_dpp(int(b >> 32), 0xB1, 0xf, 0xf, false);
+  return __longlong_as_double((long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo));
+}
+
+// Complex product of (xr, xi) with the compile-time unit number e^{2 pi i e / n}
+// (SIGN = +1) or its conjugate (SIGN = -1).
+template <long E, long NN, int SIGN, typename T>
+__device__ __forceinline__ void cmul_unit(T& xr, T& xi) {
+  constexpr CS w = cx_unit(E, NN);
+  constexpr T c = T(w.c), s = T(SIGN * w.s);
+  const T r = fmaT(c, xr, -s * xi);
+  xi = fmaT(c, xi, s * xr);
+  xr = r;
+}
+
+// Band-limited spectrum -> this lane's half of the samples (see above).
+//   x_n = sum_{|k|<=K} X_k e^{2 pi i k n / N},  Im X_0 ignored.
+// pf is 0 on lane 0 and 1 on lane 1 of the pair.  Lane-dependent factors are
+// formed as both candidates from compile-time constants followed by a select
+// of the two results (never a select between two constants, which would keep
+// the constants in registers across the caller's loops).  pf passes through an
+// empty asm statement so that nothing derived from it is hoisted either.
+template <int N, int KH, typename T>
+__device__ __forceinline__ void spec_to_phys_pair(const cplx<T> (&X)[KH], T pf, T (&out)[N / 2]) {
+  constexpr int M = N / 2, Q = M / 2;
+  static_assert(2 * KH <= M + 1, "K must be below N/2");
+  __asm__ volatile("" : "+v"(pf));
+  const bool odd = pf != T(0);
+  const T sgn = odd ? T(-1) : T(1);
+  T zr[Q], zi[Q];
+  sfor<Q>([&](auto K1) {
+    constexpr int k1 = K1;
+    // k = 2 k1 + p; its partner M - k is entry Q - k1 - p of this lane
+    constexpr int ib0 = Q - k1, ib1 = Q - k1 - 1;
+    T ar = T(0), ai = T(0);
+    if constexpr (k1 < KH) {
+      ar = X[k1].r;
+      ai = X[k1].i;
+      if constexpr (k1 == 0) ai = odd ? ai : T(0);  // Im X_0 (lane 0, entry 0)
+    }
+    T b0r = T(0), b0i = T(0), b1r = T(0), b1i = T(0);
+    if constexpr (ib0 < KH && ib0 < Q) {
+      b0r = X[ib0].r;
+      b0i = X[ib0].i;
+    }
+    if constexpr (ib1 < KH) {
+      b1r = X[ib1].r;
+      b1i = X[ib1].i;
+    }
+    const T br = odd ? b1r : b0r, bi = -(odd ? b1i : b0i);  // conj(X_{M-k})
+    const T er = ar + br, ei = ai + bi;
+    T dr = ar - br, di = ai - bi;
+    // O_k = w^k D_k, w = e^{2 pi i / N}: lane 1 takes one more factor w
+    T d1r = dr, d1i = di;
+    cmul_unit<1, N, +1, T>(d1r, d1i);
+    dr = odd ? d1r : dr;
+    di = odd ? d1i : di;
+    if constexpr (k1 != 0) cmul_unit<2 * k1, N, +1, T>(dr, di);
+    zr[k1] = er - di;  // Z_k = E_k + i O_k
+    zi[k1] = ei + dr;
+  });
+  fft_c<Q, +1, T>(zr, zi);
+  sfor<Q>([&](auto M1) {
+    constexpr int m1 = M1;
+    T tr = zr[m1], ti = zi[m1];
+    if constexpr (m1 != 0) {  // lane 1: times e^{2 pi i m1 / M}
+      T ur = tr, ui = ti;
+      cmul_unit<m1, M, +1, T>(ur, ui);
+      tr = odd ? ur : tr;
+      ti = odd ? ui : ti;
+    }
+    const T yr = pair_swap(tr), yi = pair_swap(ti);
+    out[2 * m1] = fmaT(sgn, tr, yr);      // lane 0: T0 + T1, lane 1: T0 - T1
+    out[2 * m1 + 1] = fmaT(sgn, ti, yi);
+    // keep the swaps next to their uses (clustered, their results spill)
+    if constexpr (m1 % 8 == 7) __builtin_amdgcn_sched_barrier(0);
+  });
+}
+
+// This lane's half of the samples -> its kept modes, unnormalized and doubled:
+//   X_k = 2 sum_n x_n e^{-2 pi i k n / N},  k = 2i + p <= K.
+template <int N, int KH, typename T>
+__device__ __forceinline__ void phys_to_spec2_pair(const T (&x)[N / 2], T pf, cplx<T> (&X)[KH]) {
+  constexpr int M = N / 2, Q = M / 2;
+  __asm__ volatile("" : "+v"(pf));
+  const bool odd = pf != T(0);
+  const T sgn = odd ? T(-1) : T(1);
+  T zr[Q], zi[Q];
+  sfor<Q>([&](auto M1) {
+    constexpr int m1 = M1;
+    const T xr = x[2 * m1], xi = x[2 * m1 + 1];
+    const T yr = pair_swap(xr), yi = pair_swap(xi);
+    T tr = fmaT(sgn, xr, yr), ti = fmaT(sgn, xi, yi);  // lane 0: z + z', lane 1: z - z'
+    if constexpr (m1 != 0) {  // lane 1: times e^{-2 pi i m1 / M}
+      T ur = tr, ui = ti;
+      cmul_unit<m1, M, -1, T>(ur, ui);
+      tr = odd ? ur : tr;
+      ti = odd ? ui : ti;
+    }
+    zr[m1] = tr;
+    zi[m1] = ti;
+    if constexpr (m1 % 8 == 7) __builtin_amdgcn_sched_barrier(0);
+  });
+  fft_c<Q, -1, T>(zr, zi);
+  sfor<KH>([&](auto K1) {
+    constexpr int k1 = K1;
+    // Z_{M-k} is entry (Q - k1 - p) mod Q of this lane
+    constexpr int ib0 = (Q - k1) % Q, ib1 = Q - k1 - 1;
+    const T br = odd ? zr[ib1] : zr[ib0], bi = odd ? zi[ib1] : zi[ib0];
+    const T Dr = zr[k1] + br, Di = zi[k1] - bi;
+    T Sr = zr[k1] - br, Si = zi[k1] + bi;
+    // X_k = D - i w^{-k} S: lane 1 takes one more factor w^{-1}
+    T s1r = Sr, s1i = Si;
+    cmul_unit<1, N, -1, T>(s1r, s1i);
+    Sr = odd ? s1r : Sr;
+    Si = odd ? s1i : Si;
+    if constexpr (k1 != 0) cmul_unit<2 * k1, N, -1, T>(Sr, Si);
+    X[k1].r = Dr + Si;
+    X[k1].i = Di - Sr;
+  });
+}
+
 }  // namespace ksc

@@ -23,7 +23,10 @@ __global__ __launch_bounds__(64 * W) void fused_kernel(KernelArgs<T> a) {
       tile_copy<NX, T, W>(a, cd, td.j0, tile, red);
       continue;
     }
-    tile_body<NX, T, W, MODE>(a, cd, td.curve, td.j0, tile, buf, red);
+    if constexpr (lanes_per_row<NX, T>() == 2)
+      tile_body2<NX, T, W, MODE>(a, cd, td.curve, td.j0, tile, buf);
+    else
+      tile_body<NX, T, W, MODE>(a, cd, td.curve, td.j0, tile, buf, red);
   }
 }
 
@@ -48,7 +51,12 @@ __global__ __launch_bounds__(64 * W) void mixed_kernel(KernelArgs<T> a) {
     switch (cd.n_x) {
       case 32: tile_body<32, T, W, MODE>(a, cd, td.curve, td.j0, tile, buf, red); break;
       case 64: tile_body<64, T, W, MODE>(a, cd, td.curve, td.j0, tile, buf, red); break;
-      default: tile_body<128, T, W, MODE>(a, cd, td.curve, td.j0, tile, buf, red); break;
+      default:
+        if constexpr (lanes_per_row<128, T>() == 2)
+          tile_body2<128, T, W, MODE>(a, cd, td.curve, td.j0, tile, buf);
+        else
+          tile_body<128, T, W, MODE>(a, cd, td.curve, td.j0, tile, buf, red);
+        break;
     }
   }
 }
@@ -101,26 +109,29 @@ namespace ksc {
 
 // Tile shapes whose LDS staging buffer exceeds the 160 KB of a gfx950 CU are
 // not instantiated.
-template <typename T, int W, int KM>
+template <typename T, int W, int NX>
 constexpr bool tile_fits() {
-  return ((64 * W + 2) * KM + 2) * int(sizeof(cplx<T>)) <= 160 * 1024;
+  constexpr int KM = (NX - 1) / 3 + 1;
+  constexpr int R = 64 * W / lanes_per_row<NX, T>();
+  return ((R + 2) * KM + 2) * int(sizeof(cplx<T>)) <= 160 * 1024;
 }
 
 #ifndef KSC_MIXED
 template <int NX, typename T, int W>
-static hipError_t launch_w(int mode, int grid, size_t lds, hipStream_t s, const KernelArgs<T>& a) {
-  if constexpr (!tile_fits<T, W, (NX - 1) / 3 + 1>()) {
+static hipError_t launch_w(int mode, int grid, size_t lds, hipStream_t s, const KernelArgs<T>& a,
+                           hipEvent_t e0, hipEvent_t e1) {
+  if constexpr (!tile_fits<T, W, NX>()) {
     return hipErrorInvalidValue;
   } else {
   switch (mode) {
     case MODE_J:
-      hipLaunchKernelGGL((fused_kernel<NX, T, W, MODE_J>), dim3(grid), dim3(64 * W), lds, s, a);
+      hipExtLaunchKernelGGL((fused_kernel<NX, T, W, MODE_J>), dim3(grid), dim3(64 * W), lds, s, e0, e1, 0, a);
       break;
     case MODE_GRAD:
-      hipLaunchKernelGGL((fused_kernel<NX, T, W, MODE_GRAD>), dim3(grid), dim3(64 * W), lds, s, a);
+      hipExtLaunchKernelGGL((fused_kernel<NX, T, W, MODE_GRAD>), dim3(grid), dim3(64 * W), lds, s, e0, e1, 0, a);
       break;
     default:
-      hipLaunchKernelGGL((fused_kernel<NX, T, W, MODE_STEP>), dim3(grid), dim3(64 * W), lds, s, a);
+      hipExtLaunchKernelGGL((fused_kernel<NX, T, W, MODE_STEP>), dim3(grid), dim3(64 * W), lds, s, e0, e1, 0, a);
       break;
   }
   return hipGetLastError();
@@ -128,29 +139,31 @@ static hipError_t launch_w(int mode, int grid, size_t lds, hipStream_t s, const 
 }
 
 hipError_t KSC_CAT(KSC_CAT(KSC_CAT(launch_fused_, KSC_TNAME), _), KSC_NX)(
-    int W, int mode, int grid, size_t lds, hipStream_t s, const KernelArgs<KSC_T>& a) {
+    int W, int mode, int grid, size_t lds, hipStream_t s, const KernelArgs<KSC_T>& a, hipEvent_t e0,
+    hipEvent_t e1) {
   switch (W) {
-    case 1: return launch_w<KSC_NX, KSC_T, 1>(mode, grid, lds, s, a);
-    case 2: return launch_w<KSC_NX, KSC_T, 2>(mode, grid, lds, s, a);
-    default: return launch_w<KSC_NX, KSC_T, 4>(mode, grid, lds, s, a);
+    case 1: return launch_w<KSC_NX, KSC_T, 1>(mode, grid, lds, s, a, e0, e1);
+    case 2: return launch_w<KSC_NX, KSC_T, 2>(mode, grid, lds, s, a, e0, e1);
+    default: return launch_w<KSC_NX, KSC_T, 4>(mode, grid, lds, s, a, e0, e1);
   }
 }
 
 #else
 template <typename T, int W>
-static hipError_t launch_mw(int mode, int grid, size_t lds, hipStream_t s, const KernelArgs<T>& a) {
-  if constexpr (!tile_fits<T, W, (128 - 1) / 3 + 1>()) {
+static hipError_t launch_mw(int mode, int grid, size_t lds, hipStream_t s, const KernelArgs<T>& a,
+                            hipEvent_t e0, hipEvent_t e1) {
+  if constexpr (!(tile_fits<T, W, 128>() && tile_fits<T, W, 64>())) {
     return hipErrorInvalidValue;
   } else {
   switch (mode) {
     case MODE_J:
-      hipLaunchKernelGGL((mixed_kernel<T, W, MODE_J>), dim3(grid), dim3(64 * W), lds, s, a);
+      hipExtLaunchKernelGGL((mixed_kernel<T, W, MODE_J>), dim3(grid), dim3(64 * W), lds, s, e0, e1, 0, a);
       break;
     case MODE_GRAD:
-      hipLaunchKernelGGL((mixed_kernel<T, W, MODE_GRAD>), dim3(grid), dim3(64 * W), lds, s, a);
+      hipExtLaunchKernelGGL((mixed_kernel<T, W, MODE_GRAD>), dim3(grid), dim3(64 * W), lds, s, e0, e1, 0, a);
       break;
     default:
-      hipLaunchKernelGGL((mixed_kernel<T, W, MODE_STEP>), dim3(grid), dim3(64 * W), lds, s, a);
+      hipExtLaunchKernelGGL((mixed_kernel<T, W, MODE_STEP>), dim3(grid), dim3(64 * W), lds, s, e0, e1, 0, a);
       break;
   }
   return hipGetLastError();
@@ -158,11 +171,12 @@ static hipError_t launch_mw(int mode, int grid, size_t lds, hipStream_t s, const
 }
 
 hipError_t KSC_CAT(launch_mixed_, KSC_TNAME)(int W, int mode, int grid, size_t lds, hipStream_t s,
-                                            const KernelArgs<KSC_T>& a) {
+                                            const KernelArgs<KSC_T>& a, hipEvent_t e0,
+                                            hipEvent_t e1) {
   switch (W) {
-    case 1: return launch_mw<KSC_T, 1>(mode, grid, lds, s, a);
-    case 2: return launch_mw<KSC_T, 2>(mode, grid, lds, s, a);
-    default: return launch_mw<KSC_T, 4>(mode, grid, lds, s, a);
+    case 1: return launch_mw<KSC_T, 1>(mode, grid, lds, s, a, e0, e1);
+    case 2: return launch_mw<KSC_T, 2>(mode, grid, lds, s, a, e0, e1);
+    default: return launch_mw<KSC_T, 4>(mode, grid, lds, s, a, e0, e1);
   }
 }
 

@@ -58,11 +58,21 @@ __device__ __forceinline__ bool finite_bits(double v) {
   return ((b >> 52) & 0x7ffull) != 0x7ffull;
 }
 
+// Tile boundary after tile t: row L = last row of tile t and F = L + 1 =
+// first row of tile t + 1 of the same curve.  offL < 0: nothing to finish
+// (last tile of a curve, or L or F is a pinned end row).  The row-table
+// values are stored as doubles that are exact in the run dtype.
+struct BoundDev {
+  long long offL;  // state offset (complex elements) of row L; row F follows
+  int c, km, mode_off, pad_;
+  double csL, csF, wlL, wlF;  // g/(2 dsigma) and 2 w L of rows L and F
+};
+
 template <typename T>
 struct PostArgs {
   int nc;
   const CurveDev* curves;
-  const TileDev* tiles;
+  const BoundDev* bounds;
   int n_tiles;
   const double* partials;
   const double* sqrtL;
@@ -74,14 +84,11 @@ struct PostArgs {
   int track;
   int fin_blocks;        // blocks [0, fin_blocks): one wave per curve reduces its cost
   int mode;              // MODE_GRAD / MODE_STEP: finish the tile-boundary rows
-  int rows_per_tile;
   int waves;
   int km_max;
   const cplx<T>* edge;
   const cplx<T>* in;
   cplx<T>* out;
-  const T* cs;
-  const T* wlT;
   const T* pre;
   const double* scale;
 };
@@ -138,31 +145,28 @@ __global__ __launch_bounds__(256) void post_kernel(PostArgs<T> a) {
   const long long g = (long long)(blockIdx.x - a.fin_blocks) * blockDim.x + threadIdx.x;
   const int t = int(g / a.km_max), k = int(g % a.km_max);
   if (t >= a.n_tiles - 1) return;
-  const TileDev td = a.tiles[t];
-  const int c = td.curve;
-  const CurveDev cd = a.curves[c];
-  if (k >= cd.km) return;
-  if (a.active != nullptr && a.active[c] == 0) return;
-  const int L = td.j0 + a.rows_per_tile - 1, F = L + 1;
-  if (!(L >= 1 && F <= cd.n_s - 2)) return;
+  // every load below depends only on (t, k): one round trip to memory
+  const BoundDev b = a.bounds[t];
   const long long km = a.km_max;
   const cplx<T> pL = a.edge[(t * 4ll + 2) * km + k], rL = a.edge[(t * 4ll + 3) * km + k];
   const cplx<T> pF = a.edge[((t + 1) * 4ll + 0) * km + k], rF = a.edge[((t + 1) * 4ll + 1) * km + k];
-  const T csL = a.cs[cd.row_off + L], csF = a.cs[cd.row_off + F];
+  if (b.offL < 0 || k >= b.km) return;
+  if (a.active != nullptr && a.active[b.c] == 0) return;
+  const T csL = T(b.csL), csF = T(b.csF);
   const T aLr = pL.r + csL * rF.r, aLi = pL.i + csL * rF.i;
   const T aFr = pF.r - csF * rL.r, aFi = pF.i - csF * rL.i;
-  cplx<T>* oL = a.out + cd.off + (long long)L * cd.km + k;
-  cplx<T>* oF = a.out + cd.off + (long long)F * cd.km + k;
+  cplx<T>* oL = a.out + b.offL + k;
+  cplx<T>* oF = oL + b.km;
   if (a.mode == ksc::MODE_GRAD) {
-    const T sc = a.scale ? T(a.scale[c]) : T(1);
+    const T sc = a.scale ? T(a.scale[b.c]) : T(1);
     const T ck = (k == 0) ? T(1) : T(2);
-    const T fL = ck * a.wlT[cd.row_off + L] * sc, fF = ck * a.wlT[cd.row_off + F] * sc;
+    const T fL = ck * T(b.wlL) * sc, fF = ck * T(b.wlF) * sc;
     *oL = cplx<T>{fL * aLr, (k == 0) ? T(0) : fL * aLi};
     *oF = cplx<T>{fF * aFr, (k == 0) ? T(0) : fF * aFi};
   } else {
-    const T pk = a.pre[cd.mode_off + k];
-    const cplx<T> xL = a.in[cd.off + (long long)L * cd.km + k];
-    const cplx<T> xF = a.in[cd.off + (long long)F * cd.km + k];
+    const T pk = a.pre[b.mode_off + k];
+    const cplx<T> xL = a.in[b.offL + k];
+    const cplx<T> xF = a.in[b.offL + b.km + k];
     *oL = cplx<T>{xL.r + pk * aLr, (k == 0) ? T(0) : xL.i + pk * aLi};
     *oF = cplx<T>{xF.r + pk * aFr, (k == 0) ? T(0) : xF.i + pk * aFi};
   }
@@ -197,6 +201,8 @@ struct ksc_problem {
   // device workspace
   CurveDev* d_cd = nullptr;
   TileDev* d_tiles = nullptr;
+  BoundDev* d_bounds = nullptr;
+  std::vector<double> h_cs, h_wl2;  // per-row tables (host copies, FP64)
   void* d_cs = nullptr;
   void* d_wlT = nullptr;
   double* d_wlD = nullptr;
@@ -226,47 +232,88 @@ struct ksc_problem {
     hipStream_t stream = nullptr;
   } gkey;
 
+  // kernel timing (ksc_set_timing): four events per evaluation, stamped by
+  // the fused tile kernel's and the post kernel's dispatches
+  bool timing = false;
+  bool timing_overflow = false;
+  std::vector<hipEvent_t> tev;
+  size_t tev_used = 0;
+
   size_t esize() const { return dtype == KSC_F64 ? 8 : 4; }
 };
 
 namespace {
 
-int rows_per_tile(int W) { return 64 * W; }
+// Lanes per row (mirrors lanes_per_row<NX, T>() of the kernels) and rows per
+// tile of W waves for grid size nx.
+int lanes_per_row(const ksc_problem* p, int nx) { return nx * int(p->esize()) > 512 ? 2 : 1; }
+int rows_per_tile(const ksc_problem* p, int W, int nx) { return 64 * W / lanes_per_row(p, nx); }
 
-size_t lds_bytes(const ksc_problem* p, int W, int km) {
+// LDS staging buffer of one tile: rows j0-1 .. j0+R, 16 bytes of alignment slack.
+size_t lds_for(const ksc_problem* p, int W, int nx) {
   const size_t cs = 2 * p->esize();
-  return (size_t(64 * W + 2) * km + 2) * cs;
+  return (size_t(rows_per_tile(p, W, nx) + 2) * modes_of(nx) + 2) * cs;
+}
+// Largest staging buffer over the grid sizes of the problem (one launch may
+// serve several).
+size_t lds_max(const ksc_problem* p, int W) {
+  size_t m = 0;
+  for (int nx : {8, 16, 32, 64, 128, 256})
+    if (nx >= p->min_nx && nx <= p->max_nx) m = std::max(m, lds_for(p, W, nx));
+  return m;
 }
 
-// Largest W in {4, 2, 1} (at most `cap`) whose staging buffer fits in LDS.
-int fit_W(const ksc_problem* p, int cap, int km) {
+// Largest W in {4, 2, 1} (at most `cap`) whose staging buffers fit in LDS.
+int fit_W(const ksc_problem* p, int cap) {
   for (int W : {4, 2, 1})
-    if (W <= cap && lds_bytes(p, W, km) <= p->lds_limit) return W;
+    if (W <= cap && lds_max(p, W) <= p->lds_limit) return W;
   return 0;
 }
 
 int default_W(const ksc_problem* p) {
-  // The widest tile whose staging buffer fits: 256 rows per tile keeps the
-  // tile count of a 1024-row curve at exactly 4.
-  int km = modes_of(p->max_nx);
-  if (!p->uniform && p->mixed_ok) km = modes_of(128);
-  return fit_W(p, 4, km);
+  // The widest tile that fits: 256 rows per tile keeps the tile count of a
+  // 1024-row curve at exactly 4.
+  return fit_W(p, 4);
 }
 
 ksc_status build_tiles(ksc_problem* p) {
-  const int R = rows_per_tile(p->W);
   p->tiles.clear();
   for (int c : p->curve_order) {
     CurveDev& d = p->cd[c];
+    const int R = rows_per_tile(p, p->W, d.n_x);
     const int nt = (d.n_s + R - 1) / R;
     d.tile_begin = int(p->tiles.size());
     d.n_tiles = nt;
     for (int i = 0; i < nt; ++i) p->tiles.push_back(TileDev{c, i * R});
   }
+  // boundary descriptors, one per tile (values rounded to the run dtype)
+  std::vector<BoundDev> bounds(p->tiles.size());
+  auto rt = [&](double v) { return p->dtype == KSC_F64 ? v : double(float(v)); };
+  for (size_t t = 0; t < p->tiles.size(); ++t) {
+    BoundDev& b = bounds[t];
+    b = BoundDev{-1, 0, 0, 0, 0, 0.0, 0.0, 0.0, 0.0};
+    if (t + 1 >= p->tiles.size() || p->tiles[t + 1].curve != p->tiles[t].curve) continue;
+    const CurveDev& d = p->cd[p->tiles[t].curve];
+    const int L = p->tiles[t].j0 + rows_per_tile(p, p->W, d.n_x) - 1, F = L + 1;
+    if (!(L >= 1 && F <= d.n_s - 2)) continue;
+    b.offL = d.off + (long long)L * d.km;
+    b.c = p->tiles[t].curve;
+    b.km = d.km;
+    b.mode_off = d.mode_off;
+    b.csL = rt(p->h_cs[d.row_off + L]);
+    b.csF = rt(p->h_cs[d.row_off + F]);
+    b.wlL = rt(p->h_wl2[d.row_off + L]);
+    b.wlF = rt(p->h_wl2[d.row_off + F]);
+  }
   if (p->d_tiles) hipFree(p->d_tiles);
+  if (p->d_bounds) hipFree(p->d_bounds);
   p->d_tiles = nullptr;
+  p->d_bounds = nullptr;
   KSC_HIP(hipMalloc(&p->d_tiles, p->tiles.size() * sizeof(TileDev)));
   KSC_HIP(hipMemcpy(p->d_tiles, p->tiles.data(), p->tiles.size() * sizeof(TileDev),
+                    hipMemcpyHostToDevice));
+  KSC_HIP(hipMalloc(&p->d_bounds, bounds.size() * sizeof(BoundDev)));
+  KSC_HIP(hipMemcpy(p->d_bounds, bounds.data(), bounds.size() * sizeof(BoundDev),
                     hipMemcpyHostToDevice));
   KSC_HIP(hipMemcpy(p->d_cd, p->cd.data(), p->cd.size() * sizeof(CurveDev),
                     hipMemcpyHostToDevice));
@@ -291,39 +338,39 @@ void drop_graph(ksc_problem* p) {
 
 template <typename T>
 hipError_t launch_uniform(int nx, int W, int mode, int grid, size_t lds, hipStream_t s,
-                          const KernelArgs<T>& a);
+                          const KernelArgs<T>& a, hipEvent_t e0, hipEvent_t e1);
 
 template <>
 hipError_t launch_uniform<float>(int nx, int W, int mode, int grid, size_t lds, hipStream_t s,
-                                 const KernelArgs<float>& a) {
+                                 const KernelArgs<float>& a, hipEvent_t e0, hipEvent_t e1) {
   switch (nx) {
-    case 8: return ksc::launch_fused_f32_8(W, mode, grid, lds, s, a);
-    case 16: return ksc::launch_fused_f32_16(W, mode, grid, lds, s, a);
-    case 32: return ksc::launch_fused_f32_32(W, mode, grid, lds, s, a);
-    case 64: return ksc::launch_fused_f32_64(W, mode, grid, lds, s, a);
-    case 128: return ksc::launch_fused_f32_128(W, mode, grid, lds, s, a);
-    default: return ksc::launch_fused_f32_256(W, mode, grid, lds, s, a);
+    case 8: return ksc::launch_fused_f32_8(W, mode, grid, lds, s, a, e0, e1);
+    case 16: return ksc::launch_fused_f32_16(W, mode, grid, lds, s, a, e0, e1);
+    case 32: return ksc::launch_fused_f32_32(W, mode, grid, lds, s, a, e0, e1);
+    case 64: return ksc::launch_fused_f32_64(W, mode, grid, lds, s, a, e0, e1);
+    case 128: return ksc::launch_fused_f32_128(W, mode, grid, lds, s, a, e0, e1);
+    default: return ksc::launch_fused_f32_256(W, mode, grid, lds, s, a, e0, e1);
   }
 }
 template <>
 hipError_t launch_uniform<double>(int nx, int W, int mode, int grid, size_t lds, hipStream_t s,
-                                  const KernelArgs<double>& a) {
+                                  const KernelArgs<double>& a, hipEvent_t e0, hipEvent_t e1) {
   switch (nx) {
-    case 8: return ksc::launch_fused_f64_8(W, mode, grid, lds, s, a);
-    case 16: return ksc::launch_fused_f64_16(W, mode, grid, lds, s, a);
-    case 32: return ksc::launch_fused_f64_32(W, mode, grid, lds, s, a);
-    case 64: return ksc::launch_fused_f64_64(W, mode, grid, lds, s, a);
-    case 128: return ksc::launch_fused_f64_128(W, mode, grid, lds, s, a);
-    default: return ksc::launch_fused_f64_256(W, mode, grid, lds, s, a);
+    case 8: return ksc::launch_fused_f64_8(W, mode, grid, lds, s, a, e0, e1);
+    case 16: return ksc::launch_fused_f64_16(W, mode, grid, lds, s, a, e0, e1);
+    case 32: return ksc::launch_fused_f64_32(W, mode, grid, lds, s, a, e0, e1);
+    case 64: return ksc::launch_fused_f64_64(W, mode, grid, lds, s, a, e0, e1);
+    case 128: return ksc::launch_fused_f64_128(W, mode, grid, lds, s, a, e0, e1);
+    default: return ksc::launch_fused_f64_256(W, mode, grid, lds, s, a, e0, e1);
   }
 }
 hipError_t launch_mixed(const KernelArgs<float>& a, int W, int mode, int grid, size_t lds,
-                        hipStream_t s) {
-  return ksc::launch_mixed_f32(W, mode, grid, lds, s, a);
+                        hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
+  return ksc::launch_mixed_f32(W, mode, grid, lds, s, a, e0, e1);
 }
 hipError_t launch_mixed(const KernelArgs<double>& a, int W, int mode, int grid, size_t lds,
-                        hipStream_t s) {
-  return ksc::launch_mixed_f64(W, mode, grid, lds, s, a);
+                        hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
+  return ksc::launch_mixed_f64(W, mode, grid, lds, s, a, e0, e1);
 }
 
 template <typename T>
@@ -349,19 +396,24 @@ KernelArgs<T> make_args(ksc_problem* p, const void* in, void* out, const double*
 }
 
 // Enqueue the fused kernel(s) for `mode` on stream s according to the policy.
+// ev (nullable) = {start, stop}: the first launch stamps start when it
+// begins, the last one stop when it ends.
 template <typename T>
 ksc_status launch_fused(ksc_problem* p, int mode, const void* in, void* out, const double* scale,
-                        const uint8_t* active, hipStream_t s) {
+                        const uint8_t* active, hipStream_t s, const hipEvent_t* ev) {
   KernelArgs<T> a = make_args<T>(p, in, out, scale, active);
   const int W = p->W;
+  hipEvent_t e_first = ev ? ev[0] : nullptr, e_last = ev ? ev[1] : nullptr;
   if (p->policy == KSC_LAUNCH_PLAIN) {
     for (int c = 0; c < p->nc; ++c) {
       const CurveDev& d = p->cd[c];
       KernelArgs<T> ac = a;
       ac.tile_base = d.tile_begin;
       ac.n_tiles = d.n_tiles;
-      const size_t lds = lds_bytes(p, W, d.km);
-      hipError_t e = launch_uniform<T>(d.n_x, W, mode, d.n_tiles, lds, s, ac);
+      const size_t lds = lds_for(p, W, d.n_x);
+      hipError_t e = launch_uniform<T>(d.n_x, W, mode, d.n_tiles, lds, s, ac,
+                                       c == 0 ? e_first : nullptr,
+                                       c == p->nc - 1 ? e_last : nullptr);
       if (e != hipSuccess) return fail(KSC_ERR_HIP, std::string("launch: ") + hipGetErrorString(e));
     }
     return KSC_OK;
@@ -370,14 +422,14 @@ ksc_status launch_fused(ksc_problem* p, int mode, const void* in, void* out, con
   int grid = nt;
   if (p->policy == KSC_LAUNCH_PERSISTENT) grid = std::min(nt, p->n_cu * (W == 1 ? 4 : 2));
   if (p->uniform) {
-    const size_t lds = lds_bytes(p, W, modes_of(p->max_nx));
-    hipError_t e = launch_uniform<T>(p->max_nx, W, mode, grid, lds, s, a);
+    const size_t lds = lds_for(p, W, p->max_nx);
+    hipError_t e = launch_uniform<T>(p->max_nx, W, mode, grid, lds, s, a, e_first, e_last);
     if (e != hipSuccess) return fail(KSC_ERR_HIP, std::string("launch: ") + hipGetErrorString(e));
     return KSC_OK;
   }
   if (p->mixed_ok) {
-    const size_t lds = lds_bytes(p, W, modes_of(128));
-    hipError_t e = launch_mixed(a, W, mode, grid, lds, s);
+    const size_t lds = lds_max(p, W);
+    hipError_t e = launch_mixed(a, W, mode, grid, lds, s, e_first, e_last);
     if (e != hipSuccess) return fail(KSC_ERR_HIP, std::string("launch: ") + hipGetErrorString(e));
     return KSC_OK;
   }
@@ -391,8 +443,9 @@ ksc_status launch_fused(ksc_problem* p, int mode, const void* in, void* out, con
     KernelArgs<T> ag = a;
     ag.tile_base = t0;
     ag.n_tiles = t1 - t0;
-    const size_t lds = lds_bytes(p, W, modes_of(nx));
-    hipError_t e = launch_uniform<T>(nx, W, mode, t1 - t0, lds, s, ag);
+    const size_t lds = lds_for(p, W, nx);
+    hipError_t e = launch_uniform<T>(nx, W, mode, t1 - t0, lds, s, ag,
+                                     t0 == 0 ? e_first : nullptr, t1 == nt ? e_last : nullptr);
     if (e != hipSuccess) return fail(KSC_ERR_HIP, std::string("launch: ") + hipGetErrorString(e));
     t0 = t1;
   }
@@ -402,11 +455,11 @@ ksc_status launch_fused(ksc_problem* p, int mode, const void* in, void* out, con
 template <typename T>
 ksc_status launch_post(ksc_problem* p, int mode, const void* in, void* out, const double* scale,
                        const uint8_t* active, double* J2, double* Jarc, int track,
-                       bool finalize, hipStream_t s) {
+                       bool finalize, hipStream_t s, const hipEvent_t* ev) {
   PostArgs<T> a{};
   a.nc = p->nc;
   a.curves = p->d_cd;
-  a.tiles = p->d_tiles;
+  a.bounds = p->d_bounds;
   a.n_tiles = int(p->tiles.size());
   a.partials = p->d_part;
   a.sqrtL = p->d_sqrtL;
@@ -419,39 +472,79 @@ ksc_status launch_post(ksc_problem* p, int mode, const void* in, void* out, cons
   const int b = 256;
   a.fin_blocks = finalize ? (p->nc + 3) / 4 : 0;
   a.mode = mode;
-  a.rows_per_tile = rows_per_tile(p->W);
   a.waves = p->W;
   a.km_max = p->km_max;
   a.edge = static_cast<const cplx<T>*>(p->d_edge);
   a.in = static_cast<const cplx<T>*>(in);
   a.out = static_cast<cplx<T>*>(out);
-  a.cs = static_cast<const T*>(p->d_cs);
-  a.wlT = static_cast<const T*>(p->d_wlT);
   a.pre = static_cast<const T*>(p->d_pre);
   a.scale = scale;
   const long long nfix = (mode == ksc::MODE_J) ? 0 : (long long)a.n_tiles * p->km_max;
   const int fix_blocks = int((nfix + b - 1) / b);
   const int grid = a.fin_blocks + fix_blocks;
-  if (grid == 0) return KSC_OK;
-  hipLaunchKernelGGL(post_kernel<T>, dim3(grid), dim3(b), 0, s, a);
+  if (grid == 0) {
+    // nothing to do: keep the timing pair well formed
+    if (ev) {
+      KSC_HIP(hipEventRecord(ev[0], s));
+      KSC_HIP(hipEventRecord(ev[1], s));
+    }
+    return KSC_OK;
+  }
+  hipExtLaunchKernelGGL(post_kernel<T>, dim3(grid), dim3(b), 0, s, ev ? ev[0] : nullptr,
+                        ev ? ev[1] : nullptr, 0, a);
   KSC_HIP(hipGetLastError());
   return KSC_OK;
 }
 
-// One evaluation: the fused tile kernel(s) and the post kernel.
+constexpr size_t kMaxTimedEvals = 1 << 16;
+
+// Next event of the timing pool, or nullptr when the pool is full.
+hipEvent_t timing_event(ksc_problem* p) {
+  if (p->tev_used == p->tev.size()) {
+    if (p->tev.size() >= 4 * kMaxTimedEvals) return nullptr;
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    p->tev.push_back(e);
+  }
+  return p->tev[p->tev_used++];
+}
+
+// One evaluation: the fused tile kernel(s) and the post kernel.  With timing
+// on, the dispatches themselves stamp four events: fused start/end, post
+// start/end.
 ksc_status run(ksc_problem* p, int mode, const void* in, void* out, const double* scale,
                const uint8_t* active, double* J2, double* Jarc, int track, bool finalize,
                hipStream_t s) {
+  hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
+  bool timed = false;
+  if (p->timing && s == p->stream) {
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(s, &cs) == hipSuccess && cs == hipStreamCaptureStatusNone) {
+      if (p->tev_used + 4 > 4 * kMaxTimedEvals) {
+        p->timing_overflow = true;
+      } else {
+        timed = true;
+        for (hipEvent_t& e : ev) {
+          e = timing_event(p);
+          timed = timed && e != nullptr;
+        }
+        if (!timed) p->timing_overflow = true;
+      }
+    }
+  }
+  const hipEvent_t* evf = timed ? ev : nullptr;
+  const hipEvent_t* evp = timed ? ev + 2 : nullptr;
   ksc_status st;
   if (p->dtype == KSC_F64) {
-    st = launch_fused<double>(p, mode, in, out, scale, active, s);
+    st = launch_fused<double>(p, mode, in, out, scale, active, s, evf);
     if (st == KSC_OK)
-      st = launch_post<double>(p, mode, in, out, scale, active, J2, Jarc, track, finalize, s);
+      st = launch_post<double>(p, mode, in, out, scale, active, J2, Jarc, track, finalize, s, evp);
   } else {
-    st = launch_fused<float>(p, mode, in, out, scale, active, s);
+    st = launch_fused<float>(p, mode, in, out, scale, active, s, evf);
     if (st == KSC_OK)
-      st = launch_post<float>(p, mode, in, out, scale, active, J2, Jarc, track, finalize, s);
+      st = launch_post<float>(p, mode, in, out, scale, active, J2, Jarc, track, finalize, s, evp);
   }
+  if (st != KSC_OK && timed) p->tev_used -= 4;  // drop an incomplete record
   return st;
 }
 
@@ -586,6 +679,8 @@ ksc_status ksc_create(const ksc_curve_desc* descs, int32_t n_curves, int32_t dty
     return KSC_OK;
   };
   ksc_status st;
+  p->h_cs = cs;
+  p->h_wl2 = wl2;
   if ((st = upload(&p->d_cs, cs)) != KSC_OK) return cleanup(st);
   if ((st = upload(&p->d_wlT, wl2)) != KSC_OK) return cleanup(st);
   if ((st = upload(&p->d_A, A)) != KSC_OK) return cleanup(st);
@@ -623,7 +718,8 @@ ksc_status ksc_destroy(ksc_problem* p) {
   if (!p) return fail(KSC_ERR_ARG, "ksc_destroy: null problem");
   drop_graph(p);
   if (p->cap_stream) hipStreamDestroy(p->cap_stream);
-  void* bufs[] = {p->d_cd,  p->d_tiles, p->d_cs,    p->d_wlT,    p->d_wlD,
+  for (hipEvent_t e : p->tev) hipEventDestroy(e);
+  void* bufs[] = {p->d_bounds, p->d_cd,  p->d_tiles, p->d_cs,    p->d_wlT,    p->d_wlD,
                   p->d_A,   p->d_pre,   p->d_sqrtL, p->d_part,   p->d_prevJ2,
                   p->d_flags, p->d_J2,  p->d_edge};
   for (void* b : bufs)
@@ -798,9 +894,7 @@ ksc_status ksc_set_launch(ksc_problem* p, int32_t policy, int32_t waves) {
   if (waves != 0 && waves != 1 && waves != 2 && waves != 4)
     return fail(KSC_ERR_ARG, "ksc_set_launch: waves must be 0, 1, 2 or 4");
   if (waves != 0) {
-    int km = modes_of(p->max_nx);
-    if (!p->uniform && p->mixed_ok) km = modes_of(128);
-    if (lds_bytes(p, waves, km) > p->lds_limit)
+    if (lds_max(p, waves) > p->lds_limit)
       return fail(KSC_ERR_UNSUPPORTED, "ksc_set_launch: tile does not fit in LDS");
     if (waves != p->W) {
       p->W = waves;
@@ -818,6 +912,37 @@ ksc_status ksc_get_launch(const ksc_problem* p, int32_t* policy, int32_t* waves)
   if (!p || !policy || !waves) return fail(KSC_ERR_ARG, "ksc_get_launch: null pointer");
   *policy = p->policy;
   *waves = p->W;
+  return KSC_OK;
+}
+
+ksc_status ksc_set_timing(ksc_problem* p, int32_t enable) {
+  if (!p) return fail(KSC_ERR_ARG, "ksc_set_timing: null problem");
+  p->timing = enable != 0;
+  if (p->timing) {
+    p->tev_used = 0;
+    p->timing_overflow = false;
+  }
+  return KSC_OK;
+}
+
+ksc_status ksc_read_timing(ksc_problem* p, double* fused_ms, double* post_ms, int64_t* n_evals) {
+  if (!p || !fused_ms || !post_ms || !n_evals) return fail(KSC_ERR_ARG, "ksc_read_timing: null pointer");
+  double f = 0, q = 0;
+  const size_t n = p->tev_used / 4;
+  for (size_t i = 0; i < n; ++i) {
+    hipEvent_t* e = &p->tev[4 * i];
+    KSC_HIP(hipEventSynchronize(e[3]));
+    float a = 0, b = 0;
+    KSC_HIP(hipEventElapsedTime(&a, e[0], e[1]));
+    KSC_HIP(hipEventElapsedTime(&b, e[2], e[3]));
+    f += a;
+    q += b;
+  }
+  *fused_ms = f;
+  *post_ms = q;
+  *n_evals = int64_t(n);
+  if (p->timing_overflow)
+    return fail(KSC_ERR_STATE, "ksc_read_timing: more evaluations than the timing window holds");
   return KSC_OK;
 }
 
@@ -872,15 +997,25 @@ ksc_status ksc_tune(ksc_problem* p, const char* cache_path) {
   hipEvent_t e0, e1;
   KSC_HIP(hipEventCreate(&e0));
   KSC_HIP(hipEventCreate(&e1));
-  int best_pol = p->policy, best_w = p->W;
+  // Candidates in order of preference; a later one must be at least 2% faster
+  // (best of three 10-evaluation trials) to replace the incumbent, so the
+  // choice does not flip on timing noise.
+  const bool timing = p->timing;
+  p->timing = false;
+  int best_pol = KSC_LAUNCH_AUTO, best_w = default_W(p);
   float best = 1e30f;
-  int km = modes_of(p->max_nx);
-  if (!p->uniform && p->mixed_ok) km = modes_of(128);
-  for (int pol : {KSC_LAUNCH_AUTO, KSC_LAUNCH_PERSISTENT}) {
-    for (int w : {1, 2, 4}) {
-      if (lds_bytes(p, w, km) > p->lds_limit) continue;
-      if (ksc_set_launch(p, pol, w) != KSC_OK) continue;
-      ksc_eval_grad(p, x, g, j2, nullptr);  // warm-up
+  std::vector<std::pair<int, int>> cand;
+  cand.push_back({KSC_LAUNCH_AUTO, default_W(p)});
+  for (int pol : {KSC_LAUNCH_AUTO, KSC_LAUNCH_PERSISTENT})
+    for (int w : {4, 2, 1})
+      if (!(pol == cand[0].first && w == cand[0].second)) cand.push_back({pol, w});
+  for (const auto& pw : cand) {
+    const int pol = pw.first, w = pw.second;
+    if (lds_max(p, w) > p->lds_limit) continue;
+    if (ksc_set_launch(p, pol, w) != KSC_OK) continue;
+    for (int r = 0; r < 2; ++r) ksc_eval_grad(p, x, g, j2, nullptr);  // warm-up
+    float ms_best = 1e30f;
+    for (int trial = 0; trial < 3; ++trial) {
       hipEventRecord(e0, p->stream);
       const int reps = 10;
       for (int r = 0; r < reps; ++r) ksc_eval_grad(p, x, g, j2, nullptr);
@@ -888,13 +1023,15 @@ ksc_status ksc_tune(ksc_problem* p, const char* cache_path) {
       hipEventSynchronize(e1);
       float ms = 0;
       hipEventElapsedTime(&ms, e0, e1);
-      if (ms < best) {
-        best = ms;
-        best_pol = pol;
-        best_w = w;
-      }
+      ms_best = std::min(ms_best, ms);
+    }
+    if (best == 1e30f || ms_best < 0.98f * best) {
+      best = ms_best;
+      best_pol = pol;
+      best_w = w;
     }
   }
+  p->timing = timing;
   hipEventDestroy(e0);
   hipEventDestroy(e1);
   hipFree(x);

@@ -235,16 +235,23 @@ __device__ __forceinline__ void tile_body(const KernelArgs<T>& a, const CurveDev
     {
       T v[NX];
       spec_to_phys<NX, KM, T>(In, v);
-      if (pass == 0) {
+      if constexpr (MODE == MODE_J) {  // the field is not needed again
         sfor<NX>([&](auto Nn) {
           constexpr int n = Nn;
-          u[n] = v[n];
+          v[n] = v[n] * v[n];
+        });
+      } else {
+        if (pass == 0) {
+          sfor<NX>([&](auto Nn) {
+            constexpr int n = Nn;
+            u[n] = v[n];
+          });
+        }
+        sfor<NX>([&](auto Nn) {
+          constexpr int n = Nn;
+          v[n] = u[n] * v[n];
         });
       }
-      sfor<NX>([&](auto Nn) {
-        constexpr int n = Nn;
-        v[n] = u[n] * v[n];
-      });
       phys_to_spec2<NX, KM, T>(v, S);
     }
     if (pass == 0) {
@@ -293,6 +300,9 @@ __device__ __forceinline__ void tile_body(const KernelArgs<T>& a, const CurveDev
             R[k] = interior ? cplx<T>{rr, ri} : cplx<T>{T(0), T(0)};
           }
         });
+        // finish this batch's sums here (J-only mode has no other use of the
+        // residual, and sinking its arithmetic keeps every batch's reads live)
+        __asm__ volatile("" : "+v"(rowR0), "+v"(rowR), "+v"(rowD0), "+v"(rowD));
         __builtin_amdgcn_sched_barrier(0);
       });
       double pj = 0.0, pn = 0.0, pd = 0.0;
@@ -394,13 +404,258 @@ __device__ __forceinline__ void tile_body(const KernelArgs<T>& a, const CurveDev
   }
 }
 
+// Lanes per row: one whole row per lane while its transform fits the
+// registers (N_x reals of the field kept for the adjoint plus N_x of
+// transform work space), else a lane pair per row.
+template <int NX, typename T>
+constexpr int lanes_per_row() {
+  return (NX * int(sizeof(T)) > 512) ? 2 : 1;
+}
+
+// The same evaluation with two lanes per row (lane 2r + p holds modes
+// k = 2i + p and samples [p N/2, (p+1) N/2) of row j0 + r): a tile is 32W rows.
+template <int NX, typename T, int W, int MODE>
+__device__ __forceinline__ void tile_body2(const KernelArgs<T>& a, const CurveDev& cd, int c,
+                                           int j0, int tile, cplx<T>* buf) {
+  constexpr int KM = (NX - 1) / 3 + 1;
+  constexpr int KH = (KM + 1) / 2;  // modes per lane
+  constexpr int ROWS = 32 * W;      // rows per tile
+  constexpr int NT = 64 * W;        // lanes
+  constexpr int BR = ROWS + 2;      // staged rows: j0-1 .. j0+ROWS
+  constexpr int E = 16 / int(sizeof(cplx<T>));
+  constexpr int NH = NX / 2;        // samples per lane
+  const int t = threadIdx.x >> 1;   // row within the tile
+  const int p = threadIdx.x & 1;
+  const bool odd = p != 0;
+  const T pf = T(p);
+  const int n_s = cd.n_s;
+  const int jr = j0 + t;
+  const bool interior = (jr >= 1) && (jr <= n_s - 2);
+
+  const long long base = cd.off + (long long)(j0 - 1) * KM;
+  const int sh = int(((base % E) + E) % E);
+  __syncthreads();
+  stage_block<T, NT, BR * KM + E>(buf, a.in, base, sh, BR * KM + sh,
+                                  cd.off + (long long)(j0 > 0 ? j0 - 1 : 0) * KM,
+                                  cd.off + (long long)min(n_s, j0 + ROWS + 1) * KM);
+  __syncthreads();
+  cplx<T>* __restrict__ rows = buf + sh;
+  // this lane's entry i of a row is mode 2i + p; the last entry of lane 1 may
+  // lie past K (odd KM): it reads as zero and is never written
+  auto ok = [&](int i) { return 2 * i + p < KM; };
+
+  const T x0i = rows[(t + 1) * KM].i;  // raw Im u_hat_0 (lane 0 uses it)
+  const T csj = interior ? a.cs[cd.row_off + jr] : T(0);
+  const T q1 = T(cd.q1);
+  const T qN1 = T(cd.q1 / (4.0 * NX));
+  const T qY1 = T(cd.q1 / (2.0 * NX));
+
+  cplx<T> In[KH];
+  sfor<KH>([&](auto Ii) {
+    constexpr int i = Ii;
+    In[i] = ok(i) ? rows[(t + 1) * KM + 2 * i + p] : cplx<T>{T(0), T(0)};
+  });
+  T u[NH];
+  cplx<T> S[KH];
+  constexpr int NPASS = (MODE == MODE_J) ? 1 : 2;
+  constexpr int CH = 7;
+  constexpr int NCH = (KH + CH - 1) / CH;
+#pragma clang loop unroll(disable)
+  for (int pass = 0; pass < NPASS; ++pass) {
+    {
+      T v[NH];
+      spec_to_phys_pair<NX, KH, T>(In, pf, v);
+      if constexpr (MODE == MODE_J) {  // the field is not needed again
+        sfor<NH>([&](auto Nn) {
+          constexpr int n = Nn;
+          v[n] = v[n] * v[n];
+        });
+      } else {
+        if (pass == 0) {
+          sfor<NH>([&](auto Nn) {
+            constexpr int n = Nn;
+            u[n] = v[n];
+          });
+        }
+        sfor<NH>([&](auto Nn) {
+          constexpr int n = Nn;
+          v[n] = u[n] * v[n];
+        });
+      }
+      phys_to_spec2_pair<NX, KH, T>(v, pf, S);
+    }
+    if (pass == 0) {
+      T rowR0 = T(0), rowR = T(0), rowD0 = T(0), rowD = T(0);
+      cplx<T> R[KH];
+      T q1_r = q1, qN1_r = qN1, pf_r = pf;
+      __asm__ volatile("" : "+v"(q1_r), "+v"(qN1_r), "+v"(pf_r));
+      sfor<NCH>([&](auto Cc) {
+        constexpr int i0 = int(Cc) * CH;
+        cplx<T> xm[CH], x0[CH], xp[CH];
+        sfor<CH>([&](auto Ii) {
+          constexpr int i = i0 + int(Ii);
+          if constexpr (i < KH) {
+            const int k = 2 * i + p;
+            const bool v = ok(i);
+            xm[Ii] = v ? rows[t * KM + k] : cplx<T>{T(0), T(0)};
+            x0[Ii] = v ? rows[(t + 1) * KM + k] : cplx<T>{T(0), T(0)};
+            xp[Ii] = v ? rows[(t + 2) * KM + k] : cplx<T>{T(0), T(0)};
+          }
+        });
+        __builtin_amdgcn_sched_barrier(0);
+        sfor<CH>([&](auto Ii) {
+          constexpr int ii = Ii;
+          constexpr int i = i0 + ii;
+          if constexpr (i < KH) {
+            const T kf = T(2 * i) + pf_r;           // mode number k = 2i + p
+            const T qn = kf * qN1_r;
+            const T qk = kf * q1_r;
+            const T q2 = qk * qk;
+            const T Ak = fmaT(-q2, q2, q2);
+            const T dr = xp[ii].r - xm[ii].r, di = xp[ii].i - xm[ii].i;
+            T rr = fmaT(-csj, dr, fmaT(Ak, x0[ii].r, qn * S[i].i));
+            T ri = fmaT(-csj, di, fmaT(Ak, x0[ii].i, -qn * S[i].r));
+            if constexpr (i == 0) {
+              // lane 0 entry 0 is mode 0: real, weight 1 in the Parseval sum
+              ri = odd ? ri : T(0);
+              const T e = fmaT(rr, rr, ri * ri);
+              rowR0 = odd ? T(0) : e;
+              rowR = odd ? e : T(0);
+              if constexpr (MODE == MODE_J) {
+                const T d = odd ? fmaT(dr, dr, di * di) : dr * dr;
+                rowD0 = odd ? T(0) : d;
+                rowD = odd ? d : T(0);
+              }
+            } else {
+              rowR = fmaT(rr, rr, fmaT(ri, ri, rowR));
+              if constexpr (MODE == MODE_J) rowD = fmaT(dr, dr, fmaT(di, di, rowD));
+            }
+            R[i] = interior ? cplx<T>{rr, ri} : cplx<T>{T(0), T(0)};
+          }
+        });
+        // finish this batch's sums here (J-only mode has no other use of the
+        // residual, and sinking its arithmetic keeps every batch's reads live)
+        __asm__ volatile("" : "+v"(rowR0), "+v"(rowR), "+v"(rowD0), "+v"(rowD));
+        __builtin_amdgcn_sched_barrier(0);
+      });
+      double pj = 0.0, pn = 0.0, pd = 0.0;
+      if (interior) {
+        // each lane holds its share of the row sums; J_arc needs whole rows
+        const double rR = double(rowR0) + 2.0 * double(rowR);
+        pj = a.wlD[cd.row_off + jr] * rR;
+        if constexpr (MODE == MODE_J) {
+          const double rD = double(rowD0) + 2.0 * double(rowD);
+          const double rRrow = rR + pair_swap(rR), rDrow = rD + pair_swap(rD);
+          pn = odd ? 0.0 : sqrt(rRrow * rDrow);
+          pd = odd ? 0.0 : sqrt(rDrow);
+        }
+      }
+      store_wave_partials<W, (MODE == MODE_J) ? 3 : 1>(pj, pn, pd, a.partials + 3ll * W * tile);
+      if constexpr (MODE != MODE_J) {
+        __syncthreads();
+        T qY1_r = qY1, pf_y = pf;
+        __asm__ volatile("" : "+v"(qY1_r), "+v"(pf_y));
+        sfor<KH>([&](auto Ii) {
+          constexpr int i = Ii;
+          if (ok(i)) rows[(t + 1) * KM + 2 * i + p] = R[i];
+          const T qk = (T(2 * i) + pf_y) * qY1_r;
+          In[i] = cplx<T>{-qk * R[i].i, qk * R[i].r};
+        });
+        for (int i = threadIdx.x; i < 2 * KM; i += NT)
+          rows[(i < KM) ? i : (BR - 2) * KM + i] = cplx<T>{T(0), T(0)};
+        __syncthreads();
+      }
+    }
+  }
+
+  if constexpr (MODE != MODE_J) {
+    const bool fix_lo = interior && t == 0 && jr - 1 >= 1;
+    const bool fix_hi = interior && t == ROWS - 1 && jr + 1 <= n_s - 2;
+    cplx<T> D[KH];
+    T q1_d = q1, pf_d = pf;
+    __asm__ volatile("" : "+v"(q1_d), "+v"(pf_d));
+    sfor<NCH>([&](auto Cc) {
+      constexpr int i0 = int(Cc) * CH;
+      cplx<T> rm[CH], r0[CH], rp[CH];
+      sfor<CH>([&](auto Ii) {
+        constexpr int i = i0 + int(Ii);
+        if constexpr (i < KH) {
+          const int k = 2 * i + p;
+          const bool v = ok(i);
+          rm[Ii] = v ? rows[t * KM + k] : cplx<T>{T(0), T(0)};
+          r0[Ii] = v ? rows[(t + 1) * KM + k] : cplx<T>{T(0), T(0)};
+          rp[Ii] = v ? rows[(t + 2) * KM + k] : cplx<T>{T(0), T(0)};
+        }
+      });
+      __builtin_amdgcn_sched_barrier(0);
+      sfor<CH>([&](auto Ii) {
+        constexpr int ii = Ii;
+        constexpr int i = i0 + ii;
+        if constexpr (i < KH) {
+          const T qk = (T(2 * i) + pf_d) * q1_d;
+          const T q2 = qk * qk;
+          const T Ak = fmaT(-q2, q2, q2);
+          D[i].r = fmaT(csj, rp[ii].r - rm[ii].r, fmaT(Ak, r0[ii].r, S[i].r));
+          const T di = fmaT(csj, rp[ii].i - rm[ii].i, fmaT(Ak, r0[ii].i, S[i].i));
+          D[i].i = (i == 0 && !odd) ? T(0) : di;
+        }
+      });
+      __builtin_amdgcn_sched_barrier(0);
+    });
+    if (fix_lo || fix_hi) {
+      int pe = p;  // (opaque: keeps the per-mode addresses below from being hoisted)
+      __asm__ volatile("" : "+v"(pe));
+      cplx<T>* e = a.edge + ((long long)tile * 4 + (fix_hi ? 2 : 0)) * a.km_max + pe;
+      cplx<T>* e2 = e + a.km_max;
+      const cplx<T>* rr = rows + (t + 1) * KM + pe;
+      sfor<KH>([&](auto Ii) {
+        constexpr int i = Ii;
+        if (ok(i)) {
+          e[2 * i] = D[i];
+          e2[2 * i] = rr[2 * i];
+        }
+      });
+    }
+    const long long obase = cd.off + (long long)j0 * KM;
+    const int osh = int(obase % E);
+    int po = p;
+    __asm__ volatile("" : "+v"(po));
+    cplx<T>* __restrict__ orow = buf + osh + t * KM + po;  // this lane's modes: orow[2i]
+    __syncthreads();
+    if constexpr (MODE == MODE_GRAD) {
+      const T sc = (a.scale != nullptr) ? T(a.scale[c]) : T(1);
+      const T f0 = interior ? a.wlT[cd.row_off + jr] * sc : T(0);
+      const T f2 = T(2) * f0;
+      sfor<KH>([&](auto Ii) {
+        constexpr int i = Ii;
+        const T f = (i == 0 && !odd) ? f0 : f2;  // c_0 = 1, c_k = 2
+        if (ok(i)) orow[2 * i] = cplx<T>{f * D[i].r, f * D[i].i};
+      });
+    } else {
+      const T* __restrict__ pv = a.pre + cd.mode_off + po;
+      const T m = interior ? T(1) : T(0);
+      sfor<KH>([&](auto Ii) {
+        constexpr int i = Ii;
+        if (ok(i)) {
+          const T f = m * pv[2 * i];
+          orow[2 * i] = cplx<T>{f * D[i].r, (i == 0 && !odd) ? -x0i : f * D[i].i};
+        }
+      });
+    }
+    __syncthreads();
+    flush_block<T, NT, MODE == MODE_STEP>(a.out, a.in, buf, obase, osh, ROWS * KM + osh, obase,
+                                          cd.off + (long long)min(n_s, j0 + ROWS) * KM);
+  }
+}
+
 // Inactive curve in a descent: the tile copies its rows unchanged.
 template <int NX, typename T, int W>
 __device__ __forceinline__ void tile_copy(const KernelArgs<T>& a, const CurveDev& cd, int j0,
                                           int tile, double* red) {
   constexpr int KM = (NX - 1) / 3 + 1;
-  const int jr = j0 + threadIdx.x;
-  if (jr < cd.n_s) {
+  constexpr int ROWS = 64 * W / lanes_per_row<NX, T>();
+  const int jr = j0 + int(threadIdx.x);
+  if (int(threadIdx.x) < ROWS && jr < cd.n_s) {
     const cplx<T>* s = a.in + cd.off + (long long)jr * KM;
     cplx<T>* d = a.out + cd.off + (long long)jr * KM;
     for (int k = 0; k < KM; ++k) d[k] = s[k];

@@ -221,3 +221,17 @@ class Problem:
         out = (ctypes.c_uint32 * self.n_curves)()
         check(lib().ksc_query_flags(self._h, out))
         return np.array(out, dtype=np.uint32)
+
+    def set_timing(self, enable: bool = True) -> None:
+        """Start (True) or stop (False) a kernel-timing window: HIP events on
+        the problem's stream around the fused tile kernel and the post kernel
+        of every eval_J / eval_grad / step call."""
+        self._sync_stream()
+        check(lib().ksc_set_timing(self._h, 1 if enable else 0))
+
+    def read_timing(self):
+        """(fused_ms_total, post_ms_total, n_evals) of the current window;
+        blocks until the recorded events completed."""
+        f, q, n = ctypes.c_double(), ctypes.c_double(), ctypes.c_int64()
+        check(lib().ksc_read_timing(self._h, ctypes.byref(f), ctypes.byref(q), ctypes.byref(n)))
+        return float(f.value), float(q.value), int(n.value)

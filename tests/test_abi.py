@@ -45,3 +45,6 @@ def test_pure_host_calls():
     assert L.ksc_destroy(None) == -1
     assert L.ksc_state_numel(None) == -1
     assert L.ksc_eval_J(None, None, None, None) == -1
+    assert L.ksc_set_timing(None, 1) == -1
+    f, q, n = ctypes.c_double(), ctypes.c_double(), ctypes.c_int64()
+    assert L.ksc_read_timing(None, ctypes.byref(f), ctypes.byref(q), ctypes.byref(n)) == -1
