@@ -32,6 +32,18 @@ sys.path.insert(0, ROOT)
 
 METRIC = "curve-point gradient evals/s (J+∇J) & % HBM roofline, batched vs plain"
 HBM_PEAK_GBS = 8000.0
+# Vector ALU peak without packed FP32 (the kernels are built without it): one
+# FP32 or FP64 FMA per lane per clock, 256 CUs x 4 SIMDs x 16 lanes x 2 flop
+# x 2.4 GHz.
+ALU_PEAK_TFLOPS = 78.6
+
+
+def flops_per_row(n_x: int) -> float:
+    """Algorithmic flops of one J + gradient row evaluation: four real
+    transforms of n_x points (2.5 n log2 n flops each, half of a complex FFT's
+    5 n log2 n) plus the pointwise and per-mode work: n_x (10 log2 n_x + 12)."""
+    import math
+    return n_x * (10 * math.log2(n_x) + 12)
 # Sources of the fused tile kernel; a traffic summary under profiles/ applies
 # only while their hash is the one recorded there.
 KERNEL_SOURCES = ("ksc_tile.hpp", "ksc_fft.hpp", "ksc_fused.hip", "ksc_launch.hpp")
@@ -209,6 +221,8 @@ def main():
     row_bytes = 2 * esz  # one complex value per kept mode and row
     alg_bytes = 2.0 * row_bytes * km_rows  # read the state, write the gradient
     achieved = alg_bytes / (kernel_ms * 1e-3) / 1e9
+    alg_flops = sum(s.n_s * flops_per_row(s.n_x) for s in specs)
+    tflops = alg_flops / (kernel_ms * 1e-3) / 1e12
     traffic = recorded_traffic(args.workload, args.dtype)
 
     out = {
@@ -225,12 +239,17 @@ def main():
         "dtype": args.dtype,
         "data": "synthetic",
         "config": dict(info, launch={"policy": policy, "waves_per_tile": waves}),
+        # The fused kernel's arithmetic intensity (~15 flop/B at n_x = 128) is
+        # above the ridge of the non-packed vector ALU (78.6 / 8 = 9.8 flop/B):
+        # it is bound by the ALU; the HBM fraction is reported beside it.
         "roofline": {
-            "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+            "bound": "alu", "achieved": tflops, "peak": ALU_PEAK_TFLOPS, "unit": "TFLOP/s",
+            "frac": tflops / ALU_PEAK_TFLOPS, "traffic": traffic,
             "kernel": "fused J+gradient tile kernel", "kernel_ms": kernel_ms,
+            "alg_flops_per_launch": alg_flops, "alg_bytes_per_launch": alg_bytes,
+            "hbm": {"achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                    "frac": achieved / HBM_PEAK_GBS},
             "post_kernel_ms": post_kernel_ms, "ms_per_step_with_events": ms_ev,
-            "alg_bytes_per_launch": alg_bytes,
             "grid_point_evals_per_s": sum((s.n_s - 2) * s.n_x for s in specs) / (ms * 1e-3),
         },
     }
@@ -291,6 +310,7 @@ def main():
                 "replicas": reps, "state_GB": Xb.numel() * esz / 1e9, "ms_per_step": msb,
                 "kernel_ms": kb, "achieved_GBs": bb / (kb * 1e-3) / 1e9,
                 "frac_hbm": bb / (kb * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                "frac_alu": alg_flops * reps / (kb * 1e-3) / 1e12 / ALU_PEAK_TFLOPS,
                 "curve_points_per_s": pts * reps / (msb * 1e-3),
             }
             del Xb, Gb, pb

@@ -20,7 +20,7 @@ __global__ __launch_bounds__(64 * W) void fused_kernel(KernelArgs<T> a) {
     const TileDev td = a.tiles[tile];
     const CurveDev cd = a.curves[td.curve];
     if (MODE == MODE_STEP && a.active != nullptr && a.active[td.curve] == 0) {
-      tile_copy<NX, T, W>(a, cd, td.j0, tile, red);
+      tile_copy<NX, T, W>(a, cd, td.curve, td.j0, tile);
       continue;
     }
     if constexpr (lanes_per_row<NX, T>() == 2)
@@ -42,9 +42,9 @@ __global__ __launch_bounds__(64 * W) void mixed_kernel(KernelArgs<T> a) {
     const CurveDev cd = a.curves[td.curve];
     if (MODE == MODE_STEP && a.active != nullptr && a.active[td.curve] == 0) {
       switch (cd.n_x) {
-        case 32: tile_copy<32, T, W>(a, cd, td.j0, tile, red); break;
-        case 64: tile_copy<64, T, W>(a, cd, td.j0, tile, red); break;
-        default: tile_copy<128, T, W>(a, cd, td.j0, tile, red); break;
+        case 32: tile_copy<32, T, W>(a, cd, td.curve, td.j0, tile); break;
+        case 64: tile_copy<64, T, W>(a, cd, td.curve, td.j0, tile); break;
+        default: tile_copy<128, T, W>(a, cd, td.curve, td.j0, tile); break;
       }
       continue;
     }

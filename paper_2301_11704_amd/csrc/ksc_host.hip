@@ -75,6 +75,7 @@ struct PostArgs {
   const BoundDev* bounds;
   int n_tiles;
   const double* partials;
+  int part_stride;       // as in KernelArgs
   const double* sqrtL;
   double* J2;            // nullable
   double* Jarc;          // nullable
@@ -117,11 +118,20 @@ __global__ __launch_bounds__(256) void post_kernel(PostArgs<T> a) {
     const int lane = threadIdx.x & 63;
     if (c >= a.nc) return;
     if (a.active != nullptr && a.active[c] == 0) return;
-    const CurveDev cd = a.curves[c];
     double s0 = 0, s1 = 0, s2 = 0;
-    const int nw = cd.n_tiles * a.waves;  // one partial triple per wave of each tile
+    long long first;
+    int nw;  // one partial triple per wave of each tile
+    if (a.part_stride > 0) {
+      // fixed stride: no descriptor read; slots past the curve's tiles hold 0
+      first = (long long)c * a.part_stride;
+      nw = a.part_stride;
+    } else {
+      const CurveDev cd = a.curves[c];
+      first = (long long)cd.tile_begin * a.waves;
+      nw = cd.n_tiles * a.waves;
+    }
     for (int t = lane; t < nw; t += 64) {
-      const double* p = a.partials + 3ll * ((long long)cd.tile_begin * a.waves + t);
+      const double* p = a.partials + 3 * (first + t);
       s0 += p[0];
       s1 += p[1];
       s2 += p[2];
@@ -212,6 +222,8 @@ struct ksc_problem {
   void* d_pre = nullptr;
   double* d_sqrtL = nullptr;
   double* d_part = nullptr;
+  int part_stride = 0;        // see KernelArgs::part_stride
+  long long part_slots = 0;   // allocated partial slots (3 doubles each)
   double* d_prevJ2 = nullptr;
   unsigned* d_flags = nullptr;
   double* d_J2 = nullptr;
@@ -318,14 +330,28 @@ ksc_status build_tiles(ksc_problem* p) {
   KSC_HIP(hipMemcpy(p->d_cd, p->cd.data(), p->cd.size() * sizeof(CurveDev),
                     hipMemcpyHostToDevice));
   if (int(p->tiles.size()) > p->part_cap) {
-    if (p->d_part) hipFree(p->d_part);
     if (p->d_edge) hipFree(p->d_edge);
-    p->d_part = nullptr;
     p->d_edge = nullptr;
     p->part_cap = int(p->tiles.size());
-    KSC_HIP(hipMalloc(&p->d_part, 3 * 4 * sizeof(double) * p->part_cap));
     KSC_HIP(hipMalloc(&p->d_edge, size_t(p->part_cap) * 4 * p->km_max * 2 * p->esize()));
   }
+  // partial-sum slots: per curve at a fixed stride unless that would take
+  // far more memory than the tile-ordered layout
+  int max_w = 0;
+  for (const CurveDev& d : p->cd) max_w = std::max(max_w, d.n_tiles * p->W);
+  const long long compact = (long long)p->tiles.size() * p->W;
+  const long long strided = (long long)p->nc * max_w;
+  p->part_stride = (strided <= 4 * compact + 65536) ? max_w : 0;
+  const long long need = p->part_stride > 0 ? strided : compact;
+  if (need > p->part_slots) {
+    if (p->d_part) hipFree(p->d_part);
+    p->d_part = nullptr;
+    p->part_slots = need;
+    KSC_HIP(hipMalloc(&p->d_part, 3 * sizeof(double) * size_t(need)));
+  }
+  // slots past a curve's tiles must read as 0 (stream-ordered after any
+  // evaluation already enqueued)
+  KSC_HIP(hipMemsetAsync(p->d_part, 0, 3 * sizeof(double) * size_t(need), p->stream));
   return KSC_OK;
 }
 
@@ -388,6 +414,7 @@ KernelArgs<T> make_args(ksc_problem* p, const void* in, void* out, const double*
   a.scale = scale;
   a.active = active;
   a.partials = p->d_part;
+  a.part_stride = p->part_stride;
   a.edge = static_cast<cplx<T>*>(p->d_edge);
   a.km_max = p->km_max;
   a.n_tiles = int(p->tiles.size());
@@ -462,6 +489,7 @@ ksc_status launch_post(ksc_problem* p, int mode, const void* in, void* out, cons
   a.bounds = p->d_bounds;
   a.n_tiles = int(p->tiles.size());
   a.partials = p->d_part;
+  a.part_stride = p->part_stride;
   a.sqrtL = p->d_sqrtL;
   a.J2 = J2;
   a.Jarc = Jarc;

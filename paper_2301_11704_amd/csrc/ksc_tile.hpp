@@ -56,6 +56,7 @@ struct KernelArgs {
   const double* __restrict__ scale;   // per curve gradient scale, nullable
   const unsigned char* __restrict__ active;  // per curve, nullable
   double* __restrict__ partials;      // per tile and wave: J^2, J_arc numerator, J_arc denominator
+  int part_stride;                    // > 0: curve c's slots start at c * part_stride; 0: tile order
   cplx<T>* __restrict__ edge;         // per tile: [2 slots][partial adjoint, residual][km_max]
   int km_max;                         // stride of the edge workspace
   int n_tiles;
@@ -83,6 +84,18 @@ __device__ __forceinline__ double wave_sum_to_lane63(double v) {
   v += dpp_f64<0x142, 0xa>(v);  // row_bcast:15 into rows 1 and 3
   v += dpp_f64<0x143, 0xc>(v);  // row_bcast:31 into rows 2 and 3
   return v;
+}
+
+// First partial-sum slot of a tile: per curve at a fixed stride (so the post
+// kernel finds a curve's slots without reading its descriptor), or in tile
+// order when that layout would waste too much memory.
+template <typename T>
+__device__ __forceinline__ double* tile_partials(const KernelArgs<T>& a, const CurveDev& cd, int c,
+                                                 int tile, int W) {
+  const long long slot = (a.part_stride > 0)
+                             ? (long long)c * a.part_stride + (long long)(tile - cd.tile_begin) * W
+                             : (long long)tile * W;
+  return a.partials + 3 * slot;
 }
 
 // Each wave stores its partial sums (J^2, J_arc numerator, denominator) of
@@ -121,10 +134,14 @@ __device__ __forceinline__ void stage_block(cplx<T>* __restrict__ buf, const cpl
   constexpr int NQ = (NMAX + E * NT - 1) / (E * NT);  // chunks per thread, at most
   const long long G0 = base - shift;             // global index of buf[0]
   const int nq = (n + E - 1) / E;
+  // (opaque thread index: the per-chunk offsets are formed here, not hoisted
+  // out of the caller's tile loop where they would stay live)
+  int tid = threadIdx.x;
+  __asm__ volatile("" : "+v"(tid));
   vec16<T> w[NQ];
 #pragma unroll
   for (int i = 0; i < NQ; ++i) {  // every load in flight before the first LDS store
-    const int q = threadIdx.x + i * NT;
+    const int q = tid + i * NT;
     const long long G = G0 + (long long)q * E;
     if (q < nq && G >= G_lo && G + E <= G_hi) {
       w[i] = *reinterpret_cast<const vec16<T>*>(g + G);
@@ -140,7 +157,7 @@ __device__ __forceinline__ void stage_block(cplx<T>* __restrict__ buf, const cpl
   }
 #pragma unroll
   for (int i = 0; i < NQ; ++i) {
-    const int q = threadIdx.x + i * NT;
+    const int q = tid + i * NT;
     if (q < nq) reinterpret_cast<vec16<T>*>(buf)[q] = w[i];
   }
 }
@@ -148,38 +165,65 @@ __device__ __forceinline__ void stage_block(cplx<T>* __restrict__ buf, const cpl
 // Write LDS rows back: global index G in [G_lo, G_hi) receives buf[G - base + shift]
 // (ADD: plus the input g_in[G], the state update of a descent step).  Chunks
 // are 16-byte aligned in both spaces; a chunk straddling the range is written
-// element by element so no row outside [G_lo, G_hi) is touched.
-template <typename T, int NT, bool ADD>
+// element by element so no row outside [G_lo, G_hi) is touched.  A thread's
+// chunks go in groups of GB: every read of a group (LDS, and global with ADD)
+// is issued before its first store, so their latencies overlap.
+template <typename T, int NT, int NMAX, bool ADD>
 __device__ __forceinline__ void flush_block(cplx<T>* __restrict__ gout,
                                             const cplx<T>* __restrict__ gin,
                                             const cplx<T>* __restrict__ buf, long long base,
                                             int shift, int n, long long G_lo, long long G_hi) {
   constexpr int E = 16 / int(sizeof(cplx<T>));
+  constexpr int NQ = (NMAX + E * NT - 1) / (E * NT);  // chunks per thread, at most
+  constexpr int GB = 8;
   const long long G0 = base - shift;
   const int nq = (n + E - 1) / E;
-  for (int q = threadIdx.x; q < nq; q += NT) {
-    const long long G = G0 + (long long)q * E;
-    if (G + E <= G_lo || G >= G_hi) continue;
-    vec16<T> w = reinterpret_cast<const vec16<T>*>(buf)[q];
-    if (G >= G_lo && G + E <= G_hi) {
-      if constexpr (ADD) {
-        const vec16<T> x = *reinterpret_cast<const vec16<T>*>(gin + G);
+  int tid = threadIdx.x;  // (opaque, as in stage_block)
+  __asm__ volatile("" : "+v"(tid));
+#pragma unroll 1
+  for (int i0 = 0; i0 < NQ; i0 += GB) {
+    vec16<T> w[GB];
 #pragma unroll
-        for (int h = 0; h < 2 * E; ++h) w.v[h] += x.v[h];
-      }
-      *reinterpret_cast<vec16<T>*>(gout + G) = w;
-    } else {
+    for (int i = 0; i < GB; ++i) {
+      const int q = tid + (i0 + i) * NT;
+      if (q < nq) w[i] = reinterpret_cast<const vec16<T>*>(buf)[q];
+    }
+    if constexpr (ADD) {
+      vec16<T> x[GB];
 #pragma unroll
-      for (int h = 0; h < E; ++h) {
-        if (G + h >= G_lo && G + h < G_hi) {
-          cplx<T> y{w.v[2 * h], w.v[2 * h + 1]};
-          if constexpr (ADD) {
-            const cplx<T> x = gin[G + h];
-            y.r += x.r;
-            y.i += x.i;
+      for (int i = 0; i < GB; ++i) {
+        const int q = tid + (i0 + i) * NT;
+        const long long G = G0 + (long long)q * E;
+        if (q < nq && G >= G_lo && G + E <= G_hi) {
+          x[i] = *reinterpret_cast<const vec16<T>*>(gin + G);
+        } else {
+#pragma unroll
+          for (int h = 0; h < E; ++h) {
+            const bool ok = q < nq && (G + h >= G_lo) && (G + h < G_hi);
+            const cplx<T> y = ok ? gin[G + h] : cplx<T>{T(0), T(0)};
+            x[i].v[2 * h] = y.r;
+            x[i].v[2 * h + 1] = y.i;
           }
-          gout[G + h] = y;
         }
+      }
+#pragma unroll
+      for (int i = 0; i < GB; ++i)
+#pragma unroll
+        for (int h = 0; h < 2 * E; ++h) w[i].v[h] += x[i].v[h];
+    }
+#pragma unroll
+    for (int i = 0; i < GB; ++i) {
+      const int q = tid + (i0 + i) * NT;
+      const long long G = G0 + (long long)q * E;
+      if (q < nq && G >= G_lo && G + E <= G_hi) {
+        // streaming store: the output is not read again by this kernel
+        typedef float f4_t __attribute__((ext_vector_type(4)));
+        __builtin_nontemporal_store(*reinterpret_cast<const f4_t*>(&w[i]),
+                                    reinterpret_cast<f4_t*>(gout + G));
+      } else if (q < nq) {
+#pragma unroll
+        for (int h = 0; h < E; ++h)
+          if (G + h >= G_lo && G + h < G_hi) gout[G + h] = cplx<T>{w[i].v[2 * h], w[i].v[2 * h + 1]};
       }
     }
   }
@@ -315,7 +359,7 @@ __device__ __forceinline__ void tile_body(const KernelArgs<T>& a, const CurveDev
           pd = sqrt(rD);
         }
       }
-      store_wave_partials<W, (MODE == MODE_J) ? 3 : 1>(pj, pn, pd, a.partials + 3ll * W * tile);
+      store_wave_partials<W, (MODE == MODE_J) ? 3 : 1>(pj, pn, pd, tile_partials(a, cd, c, tile, W));
       if constexpr (MODE != MODE_J) {
         // exchange residual rows through the staging buffer (outside rows read as 0)
         __syncthreads();
@@ -399,7 +443,7 @@ __device__ __forceinline__ void tile_body(const KernelArgs<T>& a, const CurveDev
       });
     }
     __syncthreads();
-    flush_block<T, ROWS, MODE == MODE_STEP>(a.out, a.in, buf, obase, osh, ROWS * KM + osh, obase,
+    flush_block<T, ROWS, ROWS * KM + E, MODE == MODE_STEP>(a.out, a.in, buf, obase, osh, ROWS * KM + osh, obase,
                                             cd.off + (long long)min(n_s, j0 + ROWS) * KM);
   }
 }
@@ -550,7 +594,7 @@ __device__ __forceinline__ void tile_body2(const KernelArgs<T>& a, const CurveDe
           pd = odd ? 0.0 : sqrt(rDrow);
         }
       }
-      store_wave_partials<W, (MODE == MODE_J) ? 3 : 1>(pj, pn, pd, a.partials + 3ll * W * tile);
+      store_wave_partials<W, (MODE == MODE_J) ? 3 : 1>(pj, pn, pd, tile_partials(a, cd, c, tile, W));
       if constexpr (MODE != MODE_J) {
         __syncthreads();
         T qY1_r = qY1, pf_y = pf;
@@ -643,15 +687,15 @@ __device__ __forceinline__ void tile_body2(const KernelArgs<T>& a, const CurveDe
       });
     }
     __syncthreads();
-    flush_block<T, NT, MODE == MODE_STEP>(a.out, a.in, buf, obase, osh, ROWS * KM + osh, obase,
+    flush_block<T, NT, ROWS * KM + E, MODE == MODE_STEP>(a.out, a.in, buf, obase, osh, ROWS * KM + osh, obase,
                                           cd.off + (long long)min(n_s, j0 + ROWS) * KM);
   }
 }
 
 // Inactive curve in a descent: the tile copies its rows unchanged.
 template <int NX, typename T, int W>
-__device__ __forceinline__ void tile_copy(const KernelArgs<T>& a, const CurveDev& cd, int j0,
-                                          int tile, double* red) {
+__device__ __forceinline__ void tile_copy(const KernelArgs<T>& a, const CurveDev& cd, int c, int j0,
+                                          int tile) {
   constexpr int KM = (NX - 1) / 3 + 1;
   constexpr int ROWS = 64 * W / lanes_per_row<NX, T>();
   const int jr = j0 + int(threadIdx.x);
@@ -660,7 +704,7 @@ __device__ __forceinline__ void tile_copy(const KernelArgs<T>& a, const CurveDev
     cplx<T>* d = a.out + cd.off + (long long)jr * KM;
     for (int k = 0; k < KM; ++k) d[k] = s[k];
   }
-  store_wave_partials<W, 1>(0.0, 0.0, 0.0, a.partials + 3ll * W * tile);
+  store_wave_partials<W, 1>(0.0, 0.0, 0.0, tile_partials(a, cd, c, tile, W));
 }
 
 }  // namespace ksc
