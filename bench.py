@@ -47,6 +47,9 @@ def flops_per_row(n_x: int) -> float:
 # Sources of the fused tile kernel; a traffic summary under profiles/ applies
 # only while their hash is the one recorded there.
 KERNEL_SOURCES = ("ksc_tile.hpp", "ksc_fft.hpp", "ksc_fused.hip", "ksc_launch.hpp")
+# Launch shapes chosen by the autotuner (ksc_tune) on an MI355X for the bench
+# workloads, so that every run (and every profiler run) uses the same shape.
+TUNE_CACHE = os.path.join(ROOT, "paper_2301_11704_amd", "tuning_gfx950.json")
 STREAM_REPLICAS = {"c4": 48, "c2": 191, "c3": 20, "c1": 0}
 DTAU = {"c4": 5e-4, "c2": 1e-4, "c3": 1e-3, "c1": 1e-3}
 
@@ -160,6 +163,11 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the host oracle baseline")
     ap.add_argument("--no-extras", action="store_true", help="skip plain and streaming legs")
     ap.add_argument("--dtype", default="f32", choices=["f32", "f64"])
+    ap.add_argument("--tune-cache", default=TUNE_CACHE, metavar="PATH",
+                    help="launch-shape cache read (or, for a shape it lacks, tuned and "
+                         "appended) by the autotuner; default: the cache shipped with the package")
+    ap.add_argument("--retune", action="store_true",
+                    help="time the launch shapes now instead of reading the cache")
     ap.add_argument("--replicas", type=int, default=None,
                     help="streaming-leg replication factor (default per workload)")
     ap.add_argument("--copy-probe", type=float, default=0.0, metavar="GB",
@@ -195,7 +203,7 @@ def main():
     for c, U in enumerate(Us):
         prob.upload(X, c, U)
     G = torch.empty_like(X)
-    prob.tune(None)
+    prob.tune(None if args.retune else args.tune_cache)
     policy, waves = prob.launch
 
     def step():
@@ -238,7 +246,8 @@ def main():
         "vs_baseline": None,
         "dtype": args.dtype,
         "data": "synthetic",
-        "config": dict(info, launch={"policy": policy, "waves_per_tile": waves}),
+        "config": dict(info, launch={"policy": policy, "waves_per_tile": waves,
+                                     "tuned": "now" if args.retune else "cache"}),
         # The fused kernel's arithmetic intensity (~15 flop/B at n_x = 128) is
         # above the ridge of the non-packed vector ALU (78.6 / 8 = 9.8 flop/B):
         # it is bound by the ALU; the HBM fraction is reported beside it.

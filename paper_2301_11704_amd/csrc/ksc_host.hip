@@ -1025,9 +1025,10 @@ ksc_status ksc_tune(ksc_problem* p, const char* cache_path) {
   hipEvent_t e0, e1;
   KSC_HIP(hipEventCreate(&e0));
   KSC_HIP(hipEventCreate(&e1));
-  // Candidates in order of preference; a later one must be at least 2% faster
-  // (best of three 10-evaluation trials) to replace the incumbent, so the
-  // choice does not flip on timing noise.
+  // Candidates in order of preference; a later one must be at least 5% faster
+  // (best of five 10-evaluation trials) to replace the incumbent, so the
+  // choice does not flip on timing noise (tile shapes within a few percent of
+  // each other are common).
   const bool timing = p->timing;
   p->timing = false;
   int best_pol = KSC_LAUNCH_AUTO, best_w = default_W(p);
@@ -1043,7 +1044,7 @@ ksc_status ksc_tune(ksc_problem* p, const char* cache_path) {
     if (ksc_set_launch(p, pol, w) != KSC_OK) continue;
     for (int r = 0; r < 2; ++r) ksc_eval_grad(p, x, g, j2, nullptr);  // warm-up
     float ms_best = 1e30f;
-    for (int trial = 0; trial < 3; ++trial) {
+    for (int trial = 0; trial < 5; ++trial) {
       hipEventRecord(e0, p->stream);
       const int reps = 10;
       for (int r = 0; r < reps; ++r) ksc_eval_grad(p, x, g, j2, nullptr);
@@ -1053,7 +1054,7 @@ ksc_status ksc_tune(ksc_problem* p, const char* cache_path) {
       hipEventElapsedTime(&ms, e0, e1);
       ms_best = std::min(ms_best, ms);
     }
-    if (best == 1e30f || ms_best < 0.98f * best) {
+    if (best == 1e30f || ms_best < 0.95f * best) {
       best = ms_best;
       best_pol = pol;
       best_w = w;
