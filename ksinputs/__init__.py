@@ -67,6 +67,34 @@ def smooth_coeffs(rng: np.random.Generator, kmax: int, amp: float, n_modes: int)
     return out
 
 
+def full_spectrum_coeffs(rng: np.random.Generator, amp: float, n_modes: int) -> np.ndarray:
+    """Every kept mode populated: u_hat_k = amp (a_k - i b_k) / (1 + k), k = 0..n_modes-1,
+    a_k, b_k ~ N(0, 1); mode 0 real."""
+    a = rng.standard_normal(n_modes)
+    b = rng.standard_normal(n_modes)
+    k = np.arange(n_modes, dtype=np.float64)
+    out = amp * (a - 1j * b) / (1.0 + k)
+    out[0] = out[0].real
+    return out
+
+
+def full_spectrum_curve(n_s: int, n_modes: int, seed, amp: float = 0.3, rough: float = 0.02):
+    """A curve whose rows populate every kept mode (unlike the smooth seeded
+    states, which fill only k <= kmax): endpoints and the sin(pi sigma)
+    perturbation from full_spectrum_coeffs, plus row-to-row independent noise of
+    relative size `rough` on the interior rows (content at every s-frequency)."""
+    rng = np.random.default_rng(np.random.SeedSequence(list(seed)))
+    A = full_spectrum_coeffs(rng, amp, n_modes)
+    B = full_spectrum_coeffs(rng, amp, n_modes)
+    p = full_spectrum_coeffs(rng, amp, n_modes)
+    U = blend_curve(A, B, p, n_s)
+    k = np.arange(n_modes, dtype=np.float64)
+    noise = (rng.standard_normal((n_s - 2, n_modes)) - 1j * rng.standard_normal((n_s - 2, n_modes)))
+    U[1:-1] += rough * amp * noise / (1.0 + k)[None, :]
+    U[:, 0] = U[:, 0].real
+    return U
+
+
 def blend_curve(A: np.ndarray, B: np.ndarray, p: np.ndarray, n_s: int) -> np.ndarray:
     """u_j = (1 - sigma_j) A + sigma_j B + sin(pi sigma_j) p, sigma_j = j / (n_s - 1)."""
     sig = np.arange(n_s, dtype=np.float64) / (n_s - 1)

@@ -559,6 +559,12 @@ __device__ __forceinline__ void tile_body2(const KernelArgs<T>& a, const CurveDe
             const T dr = xp[ii].r - xm[ii].r, di = xp[ii].i - xm[ii].i;
             T rr = fmaT(-csj, dr, fmaT(Ak, x0[ii].r, qn * S[i].i));
             T ri = fmaT(-csj, di, fmaT(Ak, x0[ii].i, -qn * S[i].r));
+            if constexpr (i == KH - 1) {
+              // past K on lane 1 when K+1 is odd: the transform still produced
+              // a coefficient there, which must not enter the cost or the adjoint
+              rr = ok(i) ? rr : T(0);
+              ri = ok(i) ? ri : T(0);
+            }
             if constexpr (i == 0) {
               // lane 0 entry 0 is mode 0: real, weight 1 in the Parseval sum
               ri = odd ? ri : T(0);

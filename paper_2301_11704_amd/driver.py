@@ -109,9 +109,11 @@ def descend_to(backend, dtau: float, J_target: float = 1e-8, max_steps: int = 10
                every: int = 100, chunk: int | None = None, switch_J: float = 1e-8,
                stall_records: int = 10, fp64_finish: bool = True, Jarc_target: float | None = None,
                min_dtau: float = 1e-9, rise_tol: float = 1e-3, checkpoint: str | None = None,
-               checkpoint_every: int | None = None, resume: bool = False, log: DescentLog | None = None):
+               checkpoint_every: int | None = None, resume: bool = False, log: DescentLog | None = None,
+               progress=None):
     """Run the descent; returns (backend, DescentLog).  The returned backend may
-    be a promoted (FP64) one holding the final state."""
+    be a promoted (FP64) one holding the final state.  progress(log, J) is
+    called after every accepted chunk with the per-curve J."""
     every = max(1, int(every))
     chunk = int(chunk or every)
     chunk = max(every, (chunk // every) * every)
@@ -153,6 +155,8 @@ def descend_to(backend, dtau: float, J_target: float = 1e-8, max_steps: int = 10
         log.tau += n * dtau
         log.dtau = dtau
         log.J_history.append((log.steps, Jn.copy()))
+        if progress is not None:
+            progress(log, Jn)
         improved = Jn < best * (1 - 1e-7)
         stall = np.where(improved, 0, stall + 1)
         best = np.minimum(best, Jn)
@@ -185,3 +189,64 @@ def descend_to(backend, dtau: float, J_target: float = 1e-8, max_steps: int = 10
     if checkpoint:
         save_checkpoint(checkpoint, backend, log, active)
     return backend, log
+
+
+def main(argv=None):
+    """Descend the batched workload-4 curves (stored KS-trajectory endpoints,
+    L = 66, N_x = 128) to a target J, FP32 first and FP64 to finish, printing
+    one progress line per chunk."""
+    import argparse
+    import sys
+    import time
+
+    import torch
+
+    ap = argparse.ArgumentParser(prog="python -m paper_2301_11704_amd.driver")
+    ap.add_argument("--curves", type=int, default=64)
+    ap.add_argument("--n-s", type=int, default=1024)
+    ap.add_argument("--dtau", type=float, default=5e-4)
+    ap.add_argument("--target", type=float, default=1e-8, help="stop when J = sqrt(J2) < target")
+    ap.add_argument("--switch", type=float, default=1e-6, help="J below which FP64 takes over")
+    ap.add_argument("--stall-records", type=int, default=10)
+    ap.add_argument("--max-steps", type=int, default=4_000_000)
+    ap.add_argument("--every", type=int, default=500)
+    ap.add_argument("--chunk", type=int, default=50_000)
+    ap.add_argument("--checkpoint", default=None)
+    ap.add_argument("--resume", action="store_true")
+    args = ap.parse_args(argv)
+
+    import ksinputs
+    from . import CurveDesc, Problem
+
+    specs, Us = ksinputs.config4_curves(args.curves, args.n_s)
+    prob = Problem([CurveDesc(s.n_s, s.n_x, s.L, s.map, s.scale, s.s0) for s in specs],
+                   dtype=torch.float32)
+    prob.tune(None)
+    X = prob.new_state()
+    for c, U in enumerate(Us):
+        prob.upload(X, c, U)
+    b = GpuBackend(prob, X)
+    t0 = time.time()
+    J0 = np.sqrt(b.J2())
+    print(f"start: {args.curves} curves, J max {J0.max():.3e} min {J0.min():.3e}", flush=True)
+
+    def report(log, J):
+        print(f"step {log.steps:9d} tau {log.tau:10.3f} {log.dtype} dtau {log.dtau:.2e} "
+              f"J max {np.max(J):.3e} min {np.min(J):.3e} converged {int(np.sum(J < args.target))}"
+              f" wall {time.time() - t0:7.1f}s", flush=True)
+
+    b2, log = descend_to(b, dtau=args.dtau, J_target=args.target, max_steps=args.max_steps,
+                         every=args.every, chunk=args.chunk, switch_J=args.switch,
+                         stall_records=args.stall_records, checkpoint=args.checkpoint,
+                         resume=args.resume, progress=report)
+    J = np.sqrt(np.abs(b2.J2()))
+    print(f"done: steps {log.steps} tau {log.tau:.3f} dtype {log.dtype} J max {J.max():.3e} "
+          f"converged {int(np.sum(J < args.target))}/{len(J)} wall {time.time() - t0:.1f}s",
+          flush=True)
+    for st, ev in log.events[-10:]:
+        print(f"  event at step {st}: {ev}", flush=True)
+    return 0 if np.all(J < args.target) else 1
+
+
+if __name__ == "__main__":
+    raise SystemExit(main())

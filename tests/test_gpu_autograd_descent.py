@@ -82,6 +82,29 @@ def test_autograd_path_workload_vs_fd_and_oracle():
     assert worst <= 1e-5, worst
 
 
+def test_workload4_fp64_matches_oracle():
+    """The FP64 finish evaluates the workload-4 batch (trajectory endpoints:
+    every mode populated) like the oracle: J2 of 8 curves to 1e-12 and the
+    gradient of 2 curves in the preconditioned norm."""
+    specs, Us = ksinputs.config4_curves(64)
+    prob = _prob(specs, torch.float64)
+    X = prob.new_state()
+    for c, U in enumerate(Us):
+        U = U.copy()
+        U[:, 0] = U[:, 0].real
+        prob.upload(X, c, U)
+    J2 = prob.eval_J(X).cpu().numpy()
+    G, _ = prob.eval_grad(X)
+    torch.cuda.synchronize()
+    for c in range(0, 64, 8):
+        U = prob.download(X, c)
+        cur = oracle_curve(specs[c])
+        ref = oracle.J2(cur, U)
+        assert abs(J2[c] - ref) <= 1e-12 * ref, (c, J2[c], ref)
+        if c in (0, 32):
+            assert precond_rel_err(cur, prob.download(G, c), oracle.grad(cur, U)) <= 1e-12
+
+
 @pytest.mark.parametrize("dtype,tol", [(np.float64, 1e-12), (np.float32, 1e-5)])
 def test_workload0_descent_2000_steps(dtype, tol):
     spec = ksinputs.config_specs(0)[0]

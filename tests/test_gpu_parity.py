@@ -117,6 +117,51 @@ def test_J2_and_gradient_parity(dtype, case, waves):
     assert e_dir <= tol, e_dir
 
 
+FULL = [(16, 300), (32, 300), (64, 300), (128, 300), (256, 300)]
+
+
+@pytest.mark.parametrize("dtype", [np.float64, np.float32])
+@pytest.mark.parametrize("n_x,n_s", FULL)
+@pytest.mark.parametrize("waves", [1, 4])
+def test_full_spectrum_parity(dtype, n_x, n_s, waves):
+    """Every kept mode populated and independent noise from row to row (the
+    smooth seeded states fill only k <= 6): J2, J_arc, the gradient and one
+    step against the oracle, for both lane layouts (one lane per row; a lane
+    pair for N_x = 256 and for FP64 N_x = 128) and for odd and even K+1."""
+    print(f"full spectrum n_x={n_x} n_s={n_s} waves={waves} dtype={dtype.__name__}", flush=True)
+    spec = _spec(n_s, n_x, 39.0, (96, n_x), "finite", 4.0)
+    import paper_2301_11704_amd as ksc
+    try:
+        prob = _problem([spec], dtype, waves=waves)
+    except ksc.KscError as e:
+        assert e.status == -3
+        pytest.skip("tile shape exceeds LDS")
+    K1 = oracle.n_modes(n_x)
+    U = ksinputs.round_to(ksinputs.full_spectrum_curve(n_s, K1, (96, n_x, n_s)), dtype)
+    U[:, 0] = U[:, 0].real
+    X = prob.new_state()
+    prob.upload(X, 0, U)
+    c = oracle_curve(spec)
+    J2, Jarc = prob.eval_J(X, arc=True)
+    G, J2g = prob.eval_grad(X)
+    Y = torch.empty_like(X)
+    prob.step(X, Y, 1e-4)
+    torch.cuda.synchronize()
+    tol = TOL[dtype]
+    J2_ref = oracle.J2(c, U)
+    assert abs(J2.item() - J2_ref) <= tol * J2_ref
+    assert abs(J2g.item() - J2_ref) <= tol * J2_ref
+    Ja_ref = oracle.J_arc(c, U)
+    assert abs(Jarc.item() - Ja_ref) <= 10 * tol * Ja_ref
+    Gg = prob.download(G, 0)
+    Gr = oracle.grad(c, U)
+    assert precond_rel_err(c, Gg, Gr) <= tol
+    assert directional_rel_err(c, Gg, Gr, [(8, i) for i in range(8)]) <= tol
+    got = prob.download(Y, 0)
+    ref = oracle.step(c, U, 1e-4)
+    assert np.linalg.norm(got - ref) / np.linalg.norm(ref) <= tol
+
+
 @pytest.mark.parametrize("dtype", [np.float64, np.float32])
 @pytest.mark.parametrize("n_s,n_x", [(150, 64), (300, 128), (300, 256)])
 def test_step_parity(dtype, n_s, n_x):
