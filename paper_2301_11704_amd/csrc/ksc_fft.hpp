@@ -161,10 +161,12 @@ __device__ __forceinline__ void spec_to_phys(const cplx<T> (&X)[KM], T (&out)[N]
   constexpr int M = N / 2;
   static_assert(KM - 1 < M, "K must be below N/2");
   T zr[M], zi[M];
-  sfor<M>([&](auto Kk) {
+  // Z_k = E_k + i O_k with E_k = X_k + conj(X_{M-k}), O_k = w^k (X_k - conj(X_{M-k})),
+  // w = e^{2 pi i / N}.  For the partner M - k, E_{M-k} = conj(E_k) and, since
+  // w^{M-k} = -conj(w^k), O_{M-k} = conj(O_k): one product serves both.
+  sfor<M / 2 + 1>([&](auto Kk) {
     constexpr int k = Kk;
     constexpr int kb = M - k;  // partner index; kb == M means X_M (zero)
-    // E_k = X_k + conj(X_{M-k}),  O_k = w^k (X_k - conj(X_{M-k})),  w = e^{2 pi i / N}
     T ar = T(0), ai = T(0), br = T(0), bi = T(0);
     if constexpr (k < KM) {
       ar = X[k].r;
@@ -176,19 +178,22 @@ __device__ __forceinline__ void spec_to_phys(const cplx<T> (&X)[KM], T (&out)[N]
     }
     T er = ar + br, ei = ai + bi;
     T dr = ar - br, di = ai - bi;
-    constexpr CS w = cx_unit(k, N);
-    constexpr T wr = T(w.c), wi = T(w.s);
     T orr, oi;
     if constexpr (k == 0) {
       orr = dr;
       oi = di;
     } else {
+      constexpr CS w = cx_unit(k, N);
+      constexpr T wr = T(w.c), wi = T(w.s);
       orr = fmaT(wr, dr, -wi * di);
       oi = fmaT(wr, di, wi * dr);
     }
-    // Z_k = E_k + i O_k
     zr[k] = er - oi;
     zi[k] = ei + orr;
+    if constexpr (k != 0 && k != M / 2) {
+      zr[M - k] = er + oi;   // conj(E) + i conj(O)
+      zi[M - k] = orr - ei;
+    }
   });
   fft_c<M, +1, T>(zr, zi);
   sfor<M>([&](auto Mm) {
@@ -216,21 +221,30 @@ __device__ __forceinline__ void phys_to_spec2(const T (&x)[N], cplx<T> (&X)[KM])
     zi[m] = x[2 * m + 1];
   });
   fft_c<M, -1, T>(zr, zi);
+  // X_k = D_k - i V_k with D = Z_k + conj(Z_{M-k}), S = Z_k - conj(Z_{M-k}),
+  // V = w^{-k} S.  For a partner M - k that is also kept, D_{M-k} = conj(D_k),
+  // S_{M-k} = -conj(S_k) and w^{-(M-k)} = -w^k, so X_{M-k} = conj(D_k + i V_k).
   sfor<KM>([&](auto Kk) {
     constexpr int k = Kk;
     constexpr int kb = (M - k) % M;
-    // D = Z_k + conj(Z_{M-k}) = 2 E_k,  S = Z_k - conj(Z_{M-k}) = 2 i O_k
-    // 2 (E_k + w^{-k} O_k) = D - i w^{-k} S,  w^{-k} = c - i s,  -i (c - i s) = -s - i c
-    constexpr CS w = cx_unit(k, N);
-    constexpr T c = T(w.c), s = T(w.s);
+    constexpr bool paired_low = (k != 0) && (2 * k < M) && (M - k < KM);  // forms X_{M-k} too
+    constexpr bool paired_high = (2 * k > M) && (M - k < KM);           // formed by M - k
     if constexpr (k == 0) {
       X[0].r = (zr[0] + zr[0]) + (zi[0] + zi[0]);
       X[0].i = T(0);
-    } else {
+    } else if constexpr (!paired_high) {
+      constexpr CS w = cx_unit(k, N);
+      constexpr T c = T(w.c), s = T(w.s);
       const T Dr = zr[k] + zr[kb], Di = zi[k] - zi[kb];
       const T Sr = zr[k] - zr[kb], Si = zi[k] + zi[kb];
-      X[k].r = fmaT(-s, Sr, fmaT(c, Si, Dr));
-      X[k].i = fmaT(-s, Si, fmaT(-c, Sr, Di));
+      // V = (c - i s) S
+      const T Vr = fmaT(c, Sr, s * Si), Vi = fmaT(c, Si, -s * Sr);
+      X[k].r = Dr + Vi;
+      X[k].i = Di - Vr;
+      if constexpr (paired_low) {
+        X[M - k].r = Dr - Vi;
+        X[M - k].i = -(Di + Vr);
+      }
     }
   });
 }

@@ -272,7 +272,7 @@ __device__ __forceinline__ void tile_body(const KernelArgs<T>& a, const CurveDev
   T u[NX];
   cplx<T> S[KM];
   constexpr int NPASS = (MODE == MODE_J) ? 1 : 2;
-  constexpr int CH = 7;                            // modes per LDS read batch
+  constexpr int CH = 5;                            // modes per LDS read batch (15 reads)
   constexpr int NCH = (KM + CH - 1) / CH;
 #pragma clang loop unroll(disable)
   for (int pass = 0; pass < NPASS; ++pass) {
@@ -308,23 +308,32 @@ __device__ __forceinline__ void tile_body(const KernelArgs<T>& a, const CurveDev
       // of the pass loop, where they would stay live across both transforms)
       T q1s_r = q1s, qN1_r = qN1;
       __asm__ volatile("" : "+v"(q1s_r), "+v"(qN1_r));
-      sfor<NCH>([&](auto Cc) {
+      // two batches of LDS reads in flight: batch c+1 is issued before the
+      // arithmetic of batch c
+      cplx<T> xm[2][CH], x0[2][CH], xp[2][CH];
+      auto load = [&](auto Cc, auto Bb) {
         constexpr int k0 = int(Cc) * CH;
-        cplx<T> xm[CH], x0[CH], xp[CH];
         sfor<CH>([&](auto Ii) {
           constexpr int k = k0 + int(Ii);
           if constexpr (k < KM) {
-            xm[Ii] = rows[t * KM + k];
-            x0[Ii] = rows[(t + 1) * KM + k];
-            xp[Ii] = rows[(t + 2) * KM + k];
+            xm[Bb][Ii] = rows[t * KM + k];
+            x0[Bb][Ii] = rows[(t + 1) * KM + k];
+            xp[Bb][Ii] = rows[(t + 2) * KM + k];
           }
         });
+      };
+      load(std::integral_constant<int, 0>{}, std::integral_constant<int, 0>{});
+      sfor<NCH>([&](auto Cc) {
+        constexpr int k0 = int(Cc) * CH;
+        constexpr int B = int(Cc) % 2;
+        if constexpr (int(Cc) + 1 < NCH)
+          load(std::integral_constant<int, int(Cc) + 1>{}, std::integral_constant<int, 1 - B>{});
         __builtin_amdgcn_sched_barrier(0);
         sfor<CH>([&](auto Ii) {
           constexpr int i = Ii;
           constexpr int k = k0 + i;
           if constexpr (k < KM) {
-            const T dr = xp[i].r - xm[i].r;
+            const T dr = xp[B][i].r - xm[B][i].r;
             T rr, ri;
             if constexpr (k == 0) {
               rr = -csj * dr;
@@ -332,12 +341,12 @@ __device__ __forceinline__ void tile_body(const KernelArgs<T>& a, const CurveDev
               rowR0 = rr * rr;
               if constexpr (MODE == MODE_J) rowD0 = dr * dr;
             } else {
-              const T di = xp[i].i - xm[i].i;
+              const T di = xp[B][i].i - xm[B][i].i;
               const T qn = T(k) * qN1_r;
               const T q2 = T(k * k) * q1s_r;
               const T Ak = fmaT(-q2, q2, q2);
-              rr = fmaT(-csj, dr, fmaT(Ak, x0[i].r, qn * S[k].i));
-              ri = fmaT(-csj, di, fmaT(Ak, x0[i].i, -qn * S[k].r));
+              rr = fmaT(-csj, dr, fmaT(Ak, x0[B][i].r, qn * S[k].i));
+              ri = fmaT(-csj, di, fmaT(Ak, x0[B][i].i, -qn * S[k].r));
               rowR = fmaT(rr, rr, fmaT(ri, ri, rowR));
               if constexpr (MODE == MODE_J) rowD = fmaT(dr, dr, fmaT(di, di, rowD));
             }
@@ -385,17 +394,24 @@ __device__ __forceinline__ void tile_body(const KernelArgs<T>& a, const CurveDev
     cplx<T> D[KM];
     T q1s_d = q1s;
     __asm__ volatile("" : "+v"(q1s_d));
-    sfor<NCH>([&](auto Cc) {
+    cplx<T> rm[2][CH], r0[2][CH], rp[2][CH];
+    auto load_r = [&](auto Cc, auto Bb) {
       constexpr int k0 = int(Cc) * CH;
-      cplx<T> rm[CH], r0[CH], rp[CH];
       sfor<CH>([&](auto Ii) {
         constexpr int k = k0 + int(Ii);
         if constexpr (k < KM) {
-          rm[Ii] = rows[t * KM + k];
-          r0[Ii] = rows[(t + 1) * KM + k];
-          rp[Ii] = rows[(t + 2) * KM + k];
+          rm[Bb][Ii] = rows[t * KM + k];
+          r0[Bb][Ii] = rows[(t + 1) * KM + k];
+          rp[Bb][Ii] = rows[(t + 2) * KM + k];
         }
       });
+    };
+    load_r(std::integral_constant<int, 0>{}, std::integral_constant<int, 0>{});
+    sfor<NCH>([&](auto Cc) {
+      constexpr int k0 = int(Cc) * CH;
+      constexpr int B = int(Cc) % 2;
+      if constexpr (int(Cc) + 1 < NCH)
+        load_r(std::integral_constant<int, int(Cc) + 1>{}, std::integral_constant<int, 1 - B>{});
       __builtin_amdgcn_sched_barrier(0);
       sfor<CH>([&](auto Ii) {
         constexpr int i = Ii;
@@ -403,8 +419,9 @@ __device__ __forceinline__ void tile_body(const KernelArgs<T>& a, const CurveDev
         if constexpr (k < KM) {
           const T q2 = T(k * k) * q1s_d;
           const T Ak = fmaT(-q2, q2, q2);
-          D[k].r = fmaT(csj, rp[i].r - rm[i].r, fmaT(Ak, r0[i].r, S[k].r));
-          D[k].i = (k == 0) ? T(0) : fmaT(csj, rp[i].i - rm[i].i, fmaT(Ak, r0[i].i, S[k].i));
+          D[k].r = fmaT(csj, rp[B][i].r - rm[B][i].r, fmaT(Ak, r0[B][i].r, S[k].r));
+          D[k].i = (k == 0) ? T(0)
+                            : fmaT(csj, rp[B][i].i - rm[B][i].i, fmaT(Ak, r0[B][i].i, S[k].i));
         }
       });
       __builtin_amdgcn_sched_barrier(0);
