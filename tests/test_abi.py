@@ -48,3 +48,32 @@ def test_pure_host_calls():
     assert L.ksc_set_timing(None, 1) == -1
     f, q, n = ctypes.c_double(), ctypes.c_double(), ctypes.c_int64()
     assert L.ksc_read_timing(None, ctypes.byref(f), ctypes.byref(q), ctypes.byref(n)) == -1
+
+
+def test_create_validates_before_touching_the_device():
+    """Shape and argument errors of ksc_create are reported before any HIP
+    call (so they are testable without a GPU): empty batch, n_s < 3, an
+    unsupported grid, L <= 0, an unknown map, a non-positive scale."""
+    from paper_2301_11704_amd import _lib
+    if not os.path.exists(_lib.LIB_PATH):
+        pytest.skip("libksc.so not built")
+    L = _lib.lib()
+    out = ctypes.c_void_p()
+
+    def create(n_s=64, n_x=32, length=22.0, map_=0, scale=40.0, n=1):
+        arr = (_lib.CurveDescC * max(n, 1))(*[_lib.CurveDescC(n_s, n_x, length, map_, scale, 0.0)
+                                              for _ in range(max(n, 1))])
+        return L.ksc_create(arr, n, 0, None, ctypes.byref(out))
+
+    assert create(n=0) == -2
+    assert create(n_s=2) == -2
+    assert create(n_s=(1 << 26) + 1) == -2
+    assert create(n_x=48) == -3
+    assert create(n_x=512) == -3
+    assert create(length=0.0) == -1
+    assert create(length=float("nan")) == -1
+    assert create(map_=7) == -1
+    assert create(scale=0.0) == -1
+    assert b"scale" in L.ksc_last_error()
+    assert create(n_x=48) == -3 and b"n_x=48" in L.ksc_last_error()
+    assert out.value is None
