@@ -28,6 +28,12 @@ from .ks import (  # noqa: F401
     step,
     inner,
     rational_Dt,
+    odd_to_full,
+    full_to_odd,
+    J2_odd,
+    J_arc_odd,
+    grad_odd,
+    step_odd,
     from_physical_curve,
     to_physical_curve,
 )

@@ -342,3 +342,45 @@ def rational_Dt(M: int, S: float) -> np.ndarray:
     D = terms.sum(axis=2)
     D *= (2.0 / (S * (M + 1))) * np.sin(np.arange(n) * h)[:, None] ** 2
     return D
+
+# ----------------------------------------------------------------------------
+# The inversion-symmetric subspace (Sec. V.B: the residual commutes with the
+# inversion sigma, so the descent flow eq. KSE_G preserves curves that are
+# inversion symmetric about x = 0; the paper's searches run there, Sec. V.D).
+# For such a curve u(-x, s) = -u(x, s): every u_hat_k is purely imaginary and
+# the mean is zero, u_hat_k = i b_k, k = 1..K.  The state of this subspace holds
+# b (K reals per row); the functions below are the full method restricted to it.
+# ----------------------------------------------------------------------------
+
+def odd_to_full(B: np.ndarray) -> np.ndarray:
+    """[n_s, K] reals b_k -> [n_s, K+1] coefficients u_hat_k = i b_k, u_hat_0 = 0."""
+    B = np.asarray(B, dtype=np.float64)
+    U = np.zeros((B.shape[0], B.shape[1] + 1), dtype=np.complex128)
+    U[:, 1:] = 1j * B
+    return U
+
+
+def full_to_odd(U: np.ndarray) -> np.ndarray:
+    """[n_s, K+1] coefficients -> b_k = Im u_hat_k, k = 1..K."""
+    return np.asarray(U)[:, 1:].imag.astype(np.float64)
+
+
+def J2_odd(c: Curve, B: np.ndarray) -> float:
+    """J^2 of the inversion-symmetric curve b."""
+    return J2(c, odd_to_full(B))
+
+
+def J_arc_odd(c: Curve, B: np.ndarray) -> float:
+    """J_arc of the inversion-symmetric curve b."""
+    return J_arc(c, odd_to_full(B))
+
+
+def grad_odd(c: Curve, B: np.ndarray) -> np.ndarray:
+    """dJ^2/db_k: the imaginary part of the full Euclidean gradient (its real
+    part and mode 0 vanish on the subspace)."""
+    return full_to_odd(grad(c, odd_to_full(B)))
+
+
+def step_odd(c: Curve, B: np.ndarray, dtau: float) -> np.ndarray:
+    """One semi-implicit step of eq. KSE_G, which stays in the subspace."""
+    return full_to_odd(step(c, odd_to_full(B), dtau))

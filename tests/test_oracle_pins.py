@@ -397,3 +397,59 @@ def test_integral_curve_residual_converges_at_second_order():
         Js.append(np.sqrt(oracle.J2(c, U)))
     ratios = np.array(Js[:-1]) / np.array(Js[1:])
     assert np.all(np.abs(ratios - 4.0) < 0.25), (Js, ratios)
+
+
+# ---------------------------------------------------- inversion-symmetric subspace
+
+
+def _odd_curve(seed, n_s, n_x, L, map_="rational", scale=40.0):
+    c = oracle.Curve(n_s, n_x, L, map_, scale)
+    rng = np.random.default_rng(seed)
+    k = np.arange(1, c.K + 1)
+    B = rng.standard_normal((n_s, c.K)) * 0.4 / k[None, :]
+    return c, B
+
+
+def test_odd_state_is_the_sine_series():
+    """b_k = Im u_hat_k means u(x) = -2 sum_k b_k sin(q_k x): explicit sine sums
+    on the grid (no FFT) against the spectral-to-physical map."""
+    c, B = _odd_curve(31, 5, 32, 22.0)
+    x = np.arange(c.n_x) * c.L / c.n_x
+    k = np.arange(1, c.K + 1)
+    u_sines = -2.0 * (B[:, :, None] * np.sin(2 * np.pi * k[None, :, None] * x[None, None, :] / c.L)).sum(1)
+    assert np.abs(oracle.to_physical(oracle.odd_to_full(B), c.n_x) - u_sines).max() <= 1e-13
+    assert np.array_equal(oracle.full_to_odd(oracle.odd_to_full(B)), B)
+
+
+@pytest.mark.parametrize("map_,scale", [("rational", 40.0), ("finite", 5.0)])
+def test_inversion_symmetric_subspace_is_invariant(map_, scale):
+    """The residual, the gradient and the step of an inversion-symmetric curve
+    stay in the subspace (purely imaginary coefficients, zero mean), Sec. V.B."""
+    c, B = _odd_curve(32, 24, 64, 39.0, map_, scale)
+    U = oracle.odd_to_full(B)
+    r = oracle.residual(c, U)
+    assert np.abs(r.real).max() <= 1e-12 * np.abs(r).max()
+    G = oracle.grad(c, U)
+    assert np.abs(G.real).max() <= 1e-12 * np.abs(G).max()
+    assert np.abs(G[:, 0]).max() <= 1e-12 * np.abs(G).max()
+    U1 = oracle.step(c, U, 1e-3)
+    assert np.abs(U1.real).max() <= 1e-12 * np.abs(U1).max()
+
+
+def test_odd_gradient_is_the_derivative_in_b():
+    """J^2 restricted to the subspace is a quartic polynomial in b, so a
+    Richardson-extrapolated central difference along a direction in b is exact
+    up to rounding; it must equal <dJ^2/db, V>."""
+    c, B = _odd_curve(33, 20, 32, 22.0, "finite", 4.0)
+    rng = np.random.default_rng(34)
+    V = rng.standard_normal(B.shape) / np.arange(1, c.K + 1)[None, :]
+    V[0] = 0
+    V[-1] = 0
+    G = oracle.grad_odd(c, B)
+
+    def fd(h):
+        return (oracle.J2_odd(c, B + h * V) - oracle.J2_odd(c, B - h * V)) / (2 * h)
+
+    rich = (4 * fd(1e-3) - fd(2e-3)) / 3
+    dot = float(np.sum(G * V))
+    assert abs(rich - dot) <= 1e-9 * abs(dot)
