@@ -7,7 +7,9 @@ boundary rows and the FP64 per-curve cost).  Workload (default): 64 curves,
 L = 66, N_x = 128 (43 kept modes), N_s = 1024, finite map T = 20, FP32 with
 FP64 cost reduction; endpoints are stored KS-trajectory states, the interior
 is the blend plus a seeded perturbation.  --workload c1/c2/c3 selects the
-single-curve and uneven-batch shapes, --dtype f64 the FP64 finish.
+single-curve and uneven-batch shapes, --dtype f64 the FP64 finish, --space odd
+the inversion-symmetric subspace (the same curves' sine coefficients
+b_k = Im u_hat_k).
 
 Prints one JSON line.  value = curve-point evals/s = sum_c (N_s - 2) * steps / s
 over K timed steps; the roofline block uses the fused kernel's own duration
@@ -15,7 +17,8 @@ from HIP events recorded by the library around each launch (a second window
 of K steps).  Extra legs: the plain policy (one launch per curve), the fused
 descent step, the captured-graph descent loop, autograd forward+backward, the
 streaming roofline (the batch replicated past the 256 MB last-level cache) and
-the FP64 oracle timed on the host on a bounded sample.
+the same curves in the inversion-symmetric subspace, and the FP64 oracle
+timed on the host on a bounded sample.
 """
 from __future__ import annotations
 
@@ -46,9 +49,24 @@ def flops_per_row(n_x: int) -> float:
     return n_x * (10 * math.log2(n_x) + 12)
 
 
-# Sources of the fused tile kernel; a traffic summary under profiles/ applies
-# only while their hash is the one recorded there.
-KERNEL_SOURCES = ("ksc_tile.hpp", "ksc_fft.hpp", "ksc_fused.hip", "ksc_launch.hpp")
+def flops_per_row_odd(n_x: int) -> float:
+    """The same for a row of the inversion-symmetric subspace, m = n_x / 2:
+    four real DFTs of m points (2.5 m log2 m each) inside the DST-I / DCT-I
+    pairs, their pre/post-processing (about 5 m each) and the pointwise and
+    per-mode work (about 15 m): m (10 log2 m + 35)."""
+    import math
+    m = n_x // 2
+    return m * (10 * math.log2(m) + 35)
+
+
+# Sources of the fused tile kernel (full space, inversion-symmetric subspace);
+# a traffic summary under profiles/ applies only while their hash is the one
+# recorded there.
+KERNEL_SOURCES = {
+    "full": ("ksc_tile.hpp", "ksc_fft.hpp", "ksc_fused.hip", "ksc_launch.hpp"),
+    "odd": ("ksc_tile.hpp", "ksc_fft.hpp", "ksc_sym.hpp", "ksc_odd.hpp", "ksc_odd.hip",
+            "ksc_launch_odd.hpp"),
+}
 # Launch shapes chosen by the autotuner (ksc_tune) on an MI355X for the bench
 # workloads, so that every run (and every profiler run) uses the same shape.
 TUNE_CACHE = os.path.join(ROOT, "paper_2301_11704_amd", "tuning_gfx950.json")
@@ -56,20 +74,21 @@ STREAM_REPLICAS = {"c4": 48, "c2": 191, "c3": 20, "c1": 0}
 DTAU = {"c4": 5e-4, "c2": 1e-4, "c3": 1e-3, "c1": 1e-3}
 
 
-def kernel_source_hash() -> str:
+def kernel_source_hash(space: str = "full") -> str:
     import hashlib
     h = hashlib.sha256()
-    for f in KERNEL_SOURCES:
+    for f in KERNEL_SOURCES[space]:
         with open(os.path.join(ROOT, "paper_2301_11704_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()
 
 
-def recorded_traffic(workload: str, dtype: str):
+def recorded_traffic(workload: str, dtype: str, space: str = "full"):
     """HBM bytes per launch of the fused J+gradient kernel from the committed
     rocprofv3 counter summary, or None if there is none or the kernel sources
     changed since it was taken."""
-    path = os.path.join(ROOT, "profiles", f"fused_grad_{workload}_{dtype}_traffic.md")
+    kind = "fused_grad" if space == "full" else "odd_grad"
+    path = os.path.join(ROOT, "profiles", f"{kind}_{workload}_{dtype}_traffic.md")
     if not os.path.exists(path):
         return None
     kv = {}
@@ -78,7 +97,7 @@ def recorded_traffic(workload: str, dtype: str):
             if line.startswith("- ") and ": " in line:
                 k, v = line[2:].split(": ", 1)
                 kv[k.strip()] = v.strip().strip("`")
-    if kv.get("kernel_source_sha256") != kernel_source_hash():
+    if kv.get("kernel_source_sha256") != kernel_source_hash(space):
         return None
     try:
         return float(kv["hbm_bytes_per_launch"])
@@ -100,7 +119,7 @@ def _specs_and_states(workload: str):
     return specs, Us, specs[0].map
 
 
-def _describe(workload, specs):
+def _describe(workload, specs, space="full"):
     ns = [s.n_s for s in specs]
     nx = sorted(set(s.n_x for s in specs))
     return {
@@ -114,8 +133,16 @@ def _describe(workload, specs):
         "n_x": nx if len(nx) > 1 else nx[0],
         "n_s_total": int(sum(ns)),
         "curve_points": int(sum(n - 2 for n in ns)),
-        "state_MB": round(sum(n * ((s.n_x - 1) // 3 + 1) * 8 for n, s in zip(ns, specs)) / 1e6, 3),
+        # FP32 state: K+1 complex values per row, or K reals in the odd subspace
+        "state_MB": round(sum(n * ((s.n_x - 1) // 3 * 4 if space == "odd" else ((s.n_x - 1) // 3 + 1) * 8)
+                              for n, s in zip(ns, specs)) / 1e6, 3),
     }
+
+
+def odd_states(Us):
+    """The sine coefficients b_k = Im u_hat_k, k = 1..K, of full-space curves
+    (their projection onto the inversion-symmetric subspace)."""
+    return [np.ascontiguousarray(U[:, 1:].imag) for U in Us]
 
 
 def _time(torch, fn, steps, stream):
@@ -183,6 +210,54 @@ def cpu_baseline(specs, Us, budget_s=12.0, single_s=6.0):
     }
 
 
+def _alg_per_launch(specs, esz, space):
+    """Algorithmic bytes (read the state, write the gradient) and flops of one
+    J + gradient launch over the batch."""
+    if space == "odd":
+        elems = sum(s.n_s * ((s.n_x - 1) // 3) for s in specs)  # K reals per row
+        return 2.0 * esz * elems, sum(s.n_s * flops_per_row_odd(s.n_x) for s in specs)
+    elems = sum(s.n_s * ((s.n_x - 1) // 3 + 1) for s in specs)  # K+1 complex per row
+    return 2.0 * 2 * esz * elems, sum(s.n_s * flops_per_row(s.n_x) for s in specs)
+
+
+def odd_leg(ksc, torch, descs, Us, tdt, esz, specs, args, stream, full_kernel_ms):
+    """J + gradient of the same curves in the inversion-symmetric subspace:
+    step time, the kernel's own duration and its rooflines."""
+    po = ksc.Problem(descs, dtype=tdt, space="odd")
+    Xo = po.new_state()
+    for c, B in enumerate(odd_states(Us)):
+        po.upload(Xo, c, B)
+    Go = torch.empty_like(Xo)
+    po.tune(None if args.retune else args.tune_cache)
+    pol, w = po.launch
+
+    def f():
+        po.eval_grad(Xo, Go)
+
+    for _ in range(args.warmup):
+        f()
+    ms = _time(torch, f, args.steps, stream)
+    po.set_timing(True)
+    _time(torch, f, args.steps, stream)
+    fo, qo, no = po.read_timing()
+    po.set_timing(False)
+    k_ms = fo / no
+    b, fl = _alg_per_launch(specs, esz, "odd")
+    pts = sum(s.n_s - 2 for s in specs)
+    res = {
+        "ms_per_step": ms, "curve_points_per_s": pts / (ms * 1e-3), "kernel_ms": k_ms,
+        "post_kernel_ms": qo / no, "launch": {"policy": pol, "waves_per_tile": w},
+        "kernel_speedup_vs_full": full_kernel_ms / k_ms,
+        "alu": {"achieved": fl / (k_ms * 1e-3) / 1e12, "peak": ALU_PEAK_TFLOPS, "unit": "TFLOP/s",
+                "frac": fl / (k_ms * 1e-3) / 1e12 / ALU_PEAK_TFLOPS},
+        "hbm": {"achieved": b / (k_ms * 1e-3) / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": b / (k_ms * 1e-3) / 1e9 / HBM_PEAK_GBS},
+        "traffic": recorded_traffic(args.workload, args.dtype, "odd"),
+    }
+    del Xo, Go, po
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -192,6 +267,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the host oracle baseline")
     ap.add_argument("--no-extras", action="store_true", help="skip plain and streaming legs")
     ap.add_argument("--dtype", default="f32", choices=["f32", "f64"])
+    ap.add_argument("--space", default="full", choices=["full", "odd"],
+                    help="state space of the timed problem (odd: inversion-symmetric subspace)")
     ap.add_argument("--tune-cache", default=TUNE_CACHE, metavar="PATH",
                     help="launch-shape cache read (or, for a shape it lacks, tuned and "
                          "appended) by the autotuner; default: the cache shipped with the package")
@@ -227,9 +304,9 @@ def main():
     esz = 8 if args.dtype == "f64" else 4
     specs, Us, _ = _specs_and_states(args.workload)
     descs = [ksc.CurveDesc(s.n_s, s.n_x, s.L, s.map, s.scale, s.s0) for s in specs]
-    prob = ksc.Problem(descs, dtype=tdt)
+    prob = ksc.Problem(descs, dtype=tdt, space=args.space)
     X = prob.new_state()
-    for c, U in enumerate(Us):
+    for c, U in enumerate(odd_states(Us) if args.space == "odd" else Us):
         prob.upload(X, c, U)
     G = torch.empty_like(X)
     prob.tune(None if args.retune else args.tune_cache)
@@ -251,16 +328,13 @@ def main():
     kernel_ms = fused_ms / n_ev
     post_kernel_ms = post_ms / n_ev
 
-    info = _describe(args.workload, specs)
+    info = _describe(args.workload, specs, args.space)
     pts = info["curve_points"]
     value = pts / (ms * 1e-3)
-    km_rows = sum(s.n_s * ((s.n_x - 1) // 3 + 1) for s in specs)
-    row_bytes = 2 * esz  # one complex value per kept mode and row
-    alg_bytes = 2.0 * row_bytes * km_rows  # read the state, write the gradient
+    alg_bytes, alg_flops = _alg_per_launch(specs, esz, args.space)
     achieved = alg_bytes / (kernel_ms * 1e-3) / 1e9
-    alg_flops = sum(s.n_s * flops_per_row(s.n_x) for s in specs)
     tflops = alg_flops / (kernel_ms * 1e-3) / 1e12
-    traffic = recorded_traffic(args.workload, args.dtype)
+    traffic = recorded_traffic(args.workload, args.dtype, args.space)
 
     out = {
         "metric": METRIC,
@@ -275,15 +349,17 @@ def main():
         "vs_baseline": None,
         "dtype": args.dtype,
         "data": "synthetic",
-        "config": dict(info, launch={"policy": policy, "waves_per_tile": waves,
-                                     "tuned": "now" if args.retune else "cache"}),
+        "config": dict(info, space=args.space,
+                       launch={"policy": policy, "waves_per_tile": waves,
+                               "tuned": "now" if args.retune else "cache"}),
         # The fused kernel's arithmetic intensity (~15 flop/B at n_x = 128) is
         # above the ridge of the non-packed vector ALU (78.6 / 8 = 9.8 flop/B):
         # it is bound by the ALU; the HBM fraction is reported beside it.
         "roofline": {
             "bound": "alu", "achieved": tflops, "peak": ALU_PEAK_TFLOPS, "unit": "TFLOP/s",
             "frac": tflops / ALU_PEAK_TFLOPS, "traffic": traffic,
-            "kernel": "fused J+gradient tile kernel", "kernel_ms": kernel_ms,
+            "kernel": "fused J+gradient tile kernel" + (" (odd subspace)" if args.space == "odd" else ""),
+            "kernel_ms": kernel_ms,
             "alg_flops_per_launch": alg_flops, "alg_bytes_per_launch": alg_bytes,
             "hbm": {"achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                     "frac": achieved / HBM_PEAK_GBS},
@@ -327,6 +403,9 @@ def main():
                            "GBs_vs_method_minimum": alg_bytes / (ms_ag * 1e-3) / 1e9,
                            "GBs_vs_recompute_design": 1.5 * alg_bytes / (ms_ag * 1e-3) / 1e9}
         del Xr, Y
+        if args.space == "full" and not (args.dtype == "f64" and max(s.n_x for s in specs) > 128):
+            out["odd_space"] = odd_leg(ksc, torch, descs, Us, tdt, esz, specs, args, stream,
+                                       kernel_ms)
         reps = STREAM_REPLICAS[args.workload] if args.replicas is None else args.replicas
         if reps > 1:
             # the batch replicated past the caches (MALL is 256 MB)

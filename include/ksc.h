@@ -37,6 +37,16 @@
  *                A_k = q_k^2 - q_k^4, q_k = 2 pi k / L.
  *   J_arc        int |r| |u_s| ds / int |u_s| ds (eq. J_arc).
  *
+ * Inversion-symmetric subspace (state space KSC_SPACE_ODD, ksc_create2): the
+ * fields with u(-x) = -u(x), invariant under the descent because the inversion
+ * operator commutes with the residual (symmetry-preservation subsection, eq.
+ * reflection).  There u_hat_k = i b_k with real b_k, k = 1..K, and a state row
+ * is the K reals b_1..b_K (layout: curve-major, row-major, K scalars per row).
+ * Every call computes the same quantities as in the full space for the state
+ * u_hat_0 = 0, u_hat_k = i b_k: J2 and J_arc are equal, the gradient is
+ * dJ2/db_k (the imaginary part of the full gradient), and a step maps b to the
+ * imaginary parts of the full step.
+ *
  * Conventions for every call:
  *   - All data pointers are DEVICE pointers owned by the caller, except
  *     ksc_query_flags' output and the descriptor array of ksc_create, which
@@ -49,8 +59,8 @@
  *     ksc_last_error() returns a message (thread-local).  Argument, shape and
  *     support errors are detected on the host before any launch.
  *   - Supported: n_x in {8, 16, 32, 64, 128, 256}, n_s >= 3, L > 0,
- *     scale > 0.  dtype KSC_F32 computes in FP32 and accumulates J2 in FP64;
- *     KSC_F64 computes in FP64.
+ *     scale > 0; in KSC_SPACE_ODD with KSC_F64, n_x <= 128.  dtype KSC_F32
+ *     computes in FP32 and accumulates J2 in FP64; KSC_F64 computes in FP64.
  *   - Kernels are deterministic: the same inputs give bitwise-equal outputs.
  */
 #ifndef KSC_H
@@ -74,6 +84,11 @@ typedef enum {
 } ksc_status;
 
 typedef enum { KSC_F32 = 0, KSC_F64 = 1 } ksc_dtype;
+
+typedef enum {
+  KSC_SPACE_FULL = 0, /* rows of K+1 complex coefficients u_hat_0..u_hat_K */
+  KSC_SPACE_ODD = 1   /* inversion-symmetric subspace: rows of K reals b_1..b_K */
+} ksc_space;
 
 typedef enum {
   KSC_MAP_RATIONAL = 0, /* s = s0 + scale * cot(pi (1 - sigma)); scale is the paper's S */
@@ -106,6 +121,11 @@ typedef struct ksc_problem ksc_problem; /* opaque */
  * list, per-tile partials, per-curve flags.  Out: *out, freed by ksc_destroy. */
 ksc_status ksc_create(const ksc_curve_desc* descs, int32_t n_curves, int32_t dtype,
                       void* hip_stream, ksc_problem** out);
+/* The same with an explicit state space (ksc_space); ksc_create is
+ * ksc_create2 with KSC_SPACE_FULL.  KSC_ERR_ARG for an unknown space,
+ * KSC_ERR_UNSUPPORTED for KSC_SPACE_ODD with KSC_F64 and n_x = 256. */
+ksc_status ksc_create2(const ksc_curve_desc* descs, int32_t n_curves, int32_t dtype,
+                       int32_t space, void* hip_stream, ksc_problem** out);
 ksc_status ksc_destroy(ksc_problem* p);
 
 /* Change the stream later calls are enqueued on. */
@@ -122,14 +142,17 @@ int32_t ksc_n_modes(int32_t n_x);
 
 /* Write the two pinned endpoint rows of curve `curve` (the asymptotic states
  * u_- and u_+ of eq. connecting_orbit_def): a_hat -> row 0, b_hat -> row
- * n_s-1; each is K+1 interleaved complex values (device pointers). */
+ * n_s-1; each is one state row (K+1 interleaved complex values, or K reals in
+ * KSC_SPACE_ODD; device pointers). */
 ksc_status ksc_set_endpoints(ksc_problem* p, void* state, int32_t curve, const void* a_hat,
                              const void* b_hat);
 
 /* Boundary conversions between the spectral state and physical samples on the
  * grid x_n = n L / n_x (Sec. V.C.1).  phys: curve-major [n_s][n_x] scalars.
  * phys_to_spec keeps modes k <= K (u_hat_k = (1/n_x) sum_n u_n e^{-2 pi i k n / n_x});
- * spec_to_phys evaluates the band-limited field. */
+ * spec_to_phys evaluates the band-limited field.  In KSC_SPACE_ODD,
+ * phys_to_spec stores b_k = Im u_hat_k (the odd part of the samples; the even
+ * part is dropped) and spec_to_phys evaluates u_n = -2 sum_k b_k sin(q_k x_n). */
 ksc_status ksc_phys_to_spec(ksc_problem* p, const void* phys, void* state);
 ksc_status ksc_spec_to_phys(ksc_problem* p, const void* state, void* phys);
 

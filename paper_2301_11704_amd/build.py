@@ -34,12 +34,15 @@ def _hipcc() -> str:
 
 
 def units():
-    """(object name, defines) for every kernel translation unit."""
+    """(object name, source, defines) for every kernel translation unit."""
     out = []
     for tname, t in (("f32", "float"), ("f64", "double")):
+        d = [f"-DKSC_T={t}", f"-DKSC_TNAME={tname}"]
         for nx in NXS:
-            out.append((f"fused_{tname}_{nx}", [f"-DKSC_T={t}", f"-DKSC_TNAME={tname}", f"-DKSC_NX={nx}"]))
-        out.append((f"mixed_{tname}", [f"-DKSC_T={t}", f"-DKSC_TNAME={tname}", "-DKSC_MIXED"]))
+            out.append((f"fused_{tname}_{nx}", "ksc_fused.hip", d + [f"-DKSC_NX={nx}"]))
+            out.append((f"odd_{tname}_{nx}", "ksc_odd.hip", d + [f"-DKSC_NX={nx}"]))
+        out.append((f"mixed_{tname}", "ksc_fused.hip", d + ["-DKSC_MIXED"]))
+        out.append((f"oddconv_{tname}", "ksc_odd.hip", d + ["-DKSC_ODD_CONV"]))
     return out
 
 
@@ -57,9 +60,9 @@ def build(jobs: int | None = None, verbose: bool = False) -> str:
     hipcc = _hipcc()
     jobs = jobs or min(8, os.cpu_count() or 4)
     cmds = []
-    for name, defs in units():
+    for name, src, defs in units():
         obj = os.path.join(BUILD, name + ".o")
-        cmds.append([hipcc, *HIPFLAGS, *defs, "-c", os.path.join(CSRC, "ksc_fused.hip"), "-o", obj])
+        cmds.append([hipcc, *HIPFLAGS, *defs, "-c", os.path.join(CSRC, src), "-o", obj])
     host_obj = os.path.join(BUILD, "host.o")
     cmds.append([hipcc, *HIPFLAGS, "-c", os.path.join(CSRC, "ksc_host.hip"), "-o", host_obj])
     # slowest units first

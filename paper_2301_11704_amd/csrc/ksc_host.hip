@@ -15,6 +15,7 @@
 
 #include "../../include/ksc.h"
 #include "ksc_launch.hpp"
+#include "ksc_launch_odd.hpp"
 
 using ksc::cplx;
 using ksc::CurveDev;
@@ -85,6 +86,7 @@ struct PostArgs {
   int track;
   int fin_blocks;        // blocks [0, fin_blocks): one wave per curve reduces its cost
   int mode;              // MODE_GRAD / MODE_STEP: finish the tile-boundary rows
+  int odd;               // rows of K reals (inversion-symmetric subspace), modes 1..K
   int waves;
   int km_max;
   const cplx<T>* edge;
@@ -155,6 +157,30 @@ __global__ __launch_bounds__(256) void post_kernel(PostArgs<T> a) {
   const long long g = (long long)(blockIdx.x - a.fin_blocks) * blockDim.x + threadIdx.x;
   const int t = int(g / a.km_max), k = int(g % a.km_max);
   if (t >= a.n_tiles - 1) return;
+  if (a.odd) {
+    // element k of a row is mode k + 1; every kept mode has c_k = 2
+    const BoundDev b = a.bounds[t];
+    const long long km = a.km_max;
+    const T* edge = reinterpret_cast<const T*>(a.edge);
+    const T pL = edge[(t * 4ll + 2) * km + k], rL = edge[(t * 4ll + 3) * km + k];
+    const T pF = edge[((t + 1) * 4ll + 0) * km + k], rF = edge[((t + 1) * 4ll + 1) * km + k];
+    if (b.offL < 0 || k >= b.km) return;
+    if (a.active != nullptr && a.active[b.c] == 0) return;
+    const T aL = pL + T(b.csL) * rF, aF = pF - T(b.csF) * rL;
+    T* oL = reinterpret_cast<T*>(a.out) + b.offL + k;
+    T* oF = oL + b.km;
+    if (a.mode == ksc::MODE_GRAD) {
+      const T sc = a.scale ? T(a.scale[b.c]) : T(1);
+      *oL = (T(2) * (T(b.wlL) * sc)) * aL;
+      *oF = (T(2) * (T(b.wlF) * sc)) * aF;
+    } else {
+      const T pk = a.pre[b.mode_off + k + 1];
+      const T* in = reinterpret_cast<const T*>(a.in);
+      *oL = in[b.offL + k] + pk * aL;
+      *oF = in[b.offL + b.km + k] + pk * aF;
+    }
+    return;
+  }
   // every load below depends only on (t, k): one round trip to memory
   const BoundDev b = a.bounds[t];
   const long long km = a.km_max;
@@ -189,6 +215,7 @@ __global__ __launch_bounds__(256) void post_kernel(PostArgs<T> a) {
 struct ksc_problem {
   int nc = 0;
   int dtype = KSC_F32;
+  int space = KSC_SPACE_FULL;
   hipStream_t stream = nullptr;
   int device = 0;
   size_t lds_limit = 65536;
@@ -198,7 +225,7 @@ struct ksc_problem {
   std::vector<CurveDev> cd;
   std::vector<TileDev> tiles;
   std::vector<int> curve_order;  // curves in tile-list order (largest n_x first)
-  long long numel_c = 0;         // complex elements of the state
+  long long numel_c = 0;         // state elements (complex; real in the odd subspace)
   long long phys_numel = 0;
   int rows_total = 0, modes_total = 0;
   int max_nx = 0, min_nx = 1 << 30;
@@ -252,17 +279,28 @@ struct ksc_problem {
   size_t tev_used = 0;
 
   size_t esize() const { return dtype == KSC_F64 ? 8 : 4; }
+  bool odd() const { return space == KSC_SPACE_ODD; }
+  // bytes of one state element, elements per row of curve d, whole-state bytes
+  size_t elem_bytes() const { return odd() ? esize() : 2 * esize(); }
+  int row_elems(const CurveDev& d) const { return odd() ? d.km - 1 : d.km; }
+  size_t state_bytes() const { return size_t(numel_c) * elem_bytes(); }
 };
 
 namespace {
 
 // Lanes per row (mirrors lanes_per_row<NX, T>() of the kernels) and rows per
 // tile of W waves for grid size nx.
-int lanes_per_row(const ksc_problem* p, int nx) { return nx * int(p->esize()) > 512 ? 2 : 1; }
+int lanes_per_row(const ksc_problem* p, int nx) {
+  if (p->odd()) return 1;
+  return nx * int(p->esize()) > 512 ? 2 : 1;
+}
 int rows_per_tile(const ksc_problem* p, int W, int nx) { return 64 * W / lanes_per_row(p, nx); }
 
 // LDS staging buffer of one tile: rows j0-1 .. j0+R, 16 bytes of alignment slack.
 size_t lds_for(const ksc_problem* p, int W, int nx) {
+  // (odd subspace: the last 16-byte chunk of a staged block may start up to
+  // 16 bytes past the block and end 16 bytes after that)
+  if (p->odd()) return size_t(rows_per_tile(p, W, nx) + 2) * (modes_of(nx) - 1) * p->esize() + 32;
   const size_t cs = 2 * p->esize();
   return (size_t(rows_per_tile(p, W, nx) + 2) * modes_of(nx) + 2) * cs;
 }
@@ -308,9 +346,9 @@ ksc_status build_tiles(ksc_problem* p) {
     const CurveDev& d = p->cd[p->tiles[t].curve];
     const int L = p->tiles[t].j0 + rows_per_tile(p, p->W, d.n_x) - 1, F = L + 1;
     if (!(L >= 1 && F <= d.n_s - 2)) continue;
-    b.offL = d.off + (long long)L * d.km;
+    b.offL = d.off + (long long)L * p->row_elems(d);
     b.c = p->tiles[t].curve;
-    b.km = d.km;
+    b.km = p->row_elems(d);
     b.mode_off = d.mode_off;
     b.csL = rt(p->h_cs[d.row_off + L]);
     b.csF = rt(p->h_cs[d.row_off + F]);
@@ -365,6 +403,34 @@ void drop_graph(ksc_problem* p) {
 template <typename T>
 hipError_t launch_uniform(int nx, int W, int mode, int grid, size_t lds, hipStream_t s,
                           const KernelArgs<T>& a, hipEvent_t e0, hipEvent_t e1);
+template <typename T>
+hipError_t launch_odd(int nx, int W, int mode, int grid, size_t lds, hipStream_t s,
+                      const KernelArgs<T>& a, hipEvent_t e0, hipEvent_t e1);
+
+template <>
+hipError_t launch_odd<float>(int nx, int W, int mode, int grid, size_t lds, hipStream_t s,
+                             const KernelArgs<float>& a, hipEvent_t e0, hipEvent_t e1) {
+  switch (nx) {
+    case 8: return ksc::launch_odd_f32_8(W, mode, grid, lds, s, a, e0, e1);
+    case 16: return ksc::launch_odd_f32_16(W, mode, grid, lds, s, a, e0, e1);
+    case 32: return ksc::launch_odd_f32_32(W, mode, grid, lds, s, a, e0, e1);
+    case 64: return ksc::launch_odd_f32_64(W, mode, grid, lds, s, a, e0, e1);
+    case 128: return ksc::launch_odd_f32_128(W, mode, grid, lds, s, a, e0, e1);
+    default: return ksc::launch_odd_f32_256(W, mode, grid, lds, s, a, e0, e1);
+  }
+}
+template <>
+hipError_t launch_odd<double>(int nx, int W, int mode, int grid, size_t lds, hipStream_t s,
+                              const KernelArgs<double>& a, hipEvent_t e0, hipEvent_t e1) {
+  switch (nx) {
+    case 8: return ksc::launch_odd_f64_8(W, mode, grid, lds, s, a, e0, e1);
+    case 16: return ksc::launch_odd_f64_16(W, mode, grid, lds, s, a, e0, e1);
+    case 32: return ksc::launch_odd_f64_32(W, mode, grid, lds, s, a, e0, e1);
+    case 64: return ksc::launch_odd_f64_64(W, mode, grid, lds, s, a, e0, e1);
+    case 128: return ksc::launch_odd_f64_128(W, mode, grid, lds, s, a, e0, e1);
+    default: return ksc::launch_odd_f64_256(W, mode, grid, lds, s, a, e0, e1);
+  }
+}
 
 template <>
 hipError_t launch_uniform<float>(int nx, int W, int mode, int grid, size_t lds, hipStream_t s,
@@ -431,6 +497,11 @@ ksc_status launch_fused(ksc_problem* p, int mode, const void* in, void* out, con
   KernelArgs<T> a = make_args<T>(p, in, out, scale, active);
   const int W = p->W;
   hipEvent_t e_first = ev ? ev[0] : nullptr, e_last = ev ? ev[1] : nullptr;
+  auto launch_nx = [&](int nx, int grid, size_t lds, const KernelArgs<T>& ag, hipEvent_t e0,
+                       hipEvent_t e1) {
+    return p->odd() ? launch_odd<T>(nx, W, mode, grid, lds, s, ag, e0, e1)
+                    : launch_uniform<T>(nx, W, mode, grid, lds, s, ag, e0, e1);
+  };
   if (p->policy == KSC_LAUNCH_PLAIN) {
     for (int c = 0; c < p->nc; ++c) {
       const CurveDev& d = p->cd[c];
@@ -438,9 +509,8 @@ ksc_status launch_fused(ksc_problem* p, int mode, const void* in, void* out, con
       ac.tile_base = d.tile_begin;
       ac.n_tiles = d.n_tiles;
       const size_t lds = lds_for(p, W, d.n_x);
-      hipError_t e = launch_uniform<T>(d.n_x, W, mode, d.n_tiles, lds, s, ac,
-                                       c == 0 ? e_first : nullptr,
-                                       c == p->nc - 1 ? e_last : nullptr);
+      hipError_t e = launch_nx(d.n_x, d.n_tiles, lds, ac, c == 0 ? e_first : nullptr,
+                               c == p->nc - 1 ? e_last : nullptr);
       if (e != hipSuccess) return fail(KSC_ERR_HIP, std::string("launch: ") + hipGetErrorString(e));
     }
     return KSC_OK;
@@ -450,7 +520,7 @@ ksc_status launch_fused(ksc_problem* p, int mode, const void* in, void* out, con
   if (p->policy == KSC_LAUNCH_PERSISTENT) grid = std::min(nt, p->n_cu * (W == 1 ? 4 : 2));
   if (p->uniform) {
     const size_t lds = lds_for(p, W, p->max_nx);
-    hipError_t e = launch_uniform<T>(p->max_nx, W, mode, grid, lds, s, a, e_first, e_last);
+    hipError_t e = launch_nx(p->max_nx, grid, lds, a, e_first, e_last);
     if (e != hipSuccess) return fail(KSC_ERR_HIP, std::string("launch: ") + hipGetErrorString(e));
     return KSC_OK;
   }
@@ -471,8 +541,8 @@ ksc_status launch_fused(ksc_problem* p, int mode, const void* in, void* out, con
     ag.tile_base = t0;
     ag.n_tiles = t1 - t0;
     const size_t lds = lds_for(p, W, nx);
-    hipError_t e = launch_uniform<T>(nx, W, mode, t1 - t0, lds, s, ag,
-                                     t0 == 0 ? e_first : nullptr, t1 == nt ? e_last : nullptr);
+    hipError_t e = launch_nx(nx, t1 - t0, lds, ag, t0 == 0 ? e_first : nullptr,
+                             t1 == nt ? e_last : nullptr);
     if (e != hipSuccess) return fail(KSC_ERR_HIP, std::string("launch: ") + hipGetErrorString(e));
     t0 = t1;
   }
@@ -500,6 +570,7 @@ ksc_status launch_post(ksc_problem* p, int mode, const void* in, void* out, cons
   const int b = 256;
   a.fin_blocks = finalize ? (p->nc + 3) / 4 : 0;
   a.mode = mode;
+  a.odd = p->odd() ? 1 : 0;
   a.waves = p->W;
   a.km_max = p->km_max;
   a.edge = static_cast<const cplx<T>*>(p->d_edge);
@@ -608,16 +679,27 @@ int32_t ksc_n_modes(int32_t n_x) { return nx_supported(n_x) ? modes_of(n_x) : -1
 
 ksc_status ksc_create(const ksc_curve_desc* descs, int32_t n_curves, int32_t dtype,
                       void* hip_stream, ksc_problem** out) {
+  return ksc_create2(descs, n_curves, dtype, KSC_SPACE_FULL, hip_stream, out);
+}
+
+ksc_status ksc_create2(const ksc_curve_desc* descs, int32_t n_curves, int32_t dtype,
+                       int32_t space, void* hip_stream, ksc_problem** out) {
   g_err.clear();
   if (!descs || !out) return fail(KSC_ERR_ARG, "ksc_create: null pointer");
   *out = nullptr;
   if (n_curves < 1) return fail(KSC_ERR_SHAPE, "ksc_create: n_curves must be >= 1");
   if (dtype != KSC_F32 && dtype != KSC_F64) return fail(KSC_ERR_ARG, "ksc_create: bad dtype");
+  if (space != KSC_SPACE_FULL && space != KSC_SPACE_ODD)
+    return fail(KSC_ERR_ARG, "ksc_create: bad state space");
   for (int c = 0; c < n_curves; ++c) {
     const ksc_curve_desc& d = descs[c];
     if (!nx_supported(d.n_x))
       return fail(KSC_ERR_UNSUPPORTED, "ksc_create: curve " + std::to_string(c) + ": n_x=" +
                                            std::to_string(d.n_x) + " not in {8,...,256}");
+    if (space == KSC_SPACE_ODD && dtype == KSC_F64 && d.n_x > 128)
+      return fail(KSC_ERR_UNSUPPORTED, "ksc_create: curve " + std::to_string(c) +
+                                           ": the inversion-symmetric subspace in FP64 "
+                                           "supports n_x <= 128");
     if (d.n_s < 3)
       return fail(KSC_ERR_SHAPE, "ksc_create: curve " + std::to_string(c) + ": n_s < 3");
     if (d.n_s > (1 << 26))
@@ -633,6 +715,7 @@ ksc_status ksc_create(const ksc_curve_desc* descs, int32_t n_curves, int32_t dty
   auto* p = new ksc_problem();
   p->nc = n_curves;
   p->dtype = dtype;
+  p->space = space;
   p->stream = static_cast<hipStream_t>(hip_stream);
   p->desc.assign(descs, descs + n_curves);
   auto cleanup = [&](ksc_status st) {
@@ -660,7 +743,7 @@ ksc_status ksc_create(const ksc_curve_desc* descs, int32_t n_curves, int32_t dty
     cd.row_off = int(cs.size());
     cd.mode_off = int(A.size());
     cd.q1 = 2.0 * M_PI / d.L;
-    p->numel_c += (long long)d.n_s * cd.km;
+    p->numel_c += (long long)d.n_s * p->row_elems(cd);
     p->phys_numel += (long long)d.n_s * d.n_x;
     const double dsig = 1.0 / (d.n_s - 1);
     for (int j = 0; j < d.n_s; ++j) {
@@ -686,6 +769,7 @@ ksc_status ksc_create(const ksc_curve_desc* descs, int32_t n_curves, int32_t dty
     p->min_nx = std::min(p->min_nx, d.n_x);
     if (d.n_x != 32 && d.n_x != 64 && d.n_x != 128) p->mixed_ok = false;
   }
+  if (p->odd()) p->mixed_ok = false;  // one launch per distinct n_x
   p->uniform = (p->max_nx == p->min_nx);
   p->rows_total = int(cs.size());
   p->modes_total = int(A.size());
@@ -762,10 +846,12 @@ ksc_status ksc_set_stream(ksc_problem* p, void* hip_stream) {
   return KSC_OK;
 }
 
-int64_t ksc_state_numel(const ksc_problem* p) { return p ? 2 * p->numel_c : -1; }
+int64_t ksc_state_numel(const ksc_problem* p) {
+  return p ? int64_t(p->state_bytes() / p->esize()) : -1;
+}
 int64_t ksc_state_offset(const ksc_problem* p, int32_t c) {
   if (!p || c < 0 || c >= p->nc) return -1;
-  return 2 * p->cd[c].off;
+  return p->cd[c].off * int64_t(p->elem_bytes() / p->esize());
 }
 int64_t ksc_phys_numel(const ksc_problem* p) { return p ? p->phys_numel : -1; }
 int64_t ksc_phys_offset(const ksc_problem* p, int32_t c) {
@@ -778,8 +864,8 @@ ksc_status ksc_set_endpoints(ksc_problem* p, void* state, int32_t curve, const v
   if (!p || !state || !a_hat || !b_hat) return fail(KSC_ERR_ARG, "ksc_set_endpoints: null pointer");
   if (curve < 0 || curve >= p->nc) return fail(KSC_ERR_SHAPE, "ksc_set_endpoints: bad curve");
   const CurveDev& d = p->cd[curve];
-  const size_t rowb = size_t(d.km) * 2 * p->esize();
-  char* base = static_cast<char*>(state) + d.off * 2 * p->esize();
+  const size_t rowb = size_t(p->row_elems(d)) * p->elem_bytes();
+  char* base = static_cast<char*>(state) + d.off * p->elem_bytes();
   KSC_HIP(hipMemcpyAsync(base, a_hat, rowb, hipMemcpyDeviceToDevice, p->stream));
   KSC_HIP(hipMemcpyAsync(base + size_t(d.n_s - 1) * rowb, b_hat, rowb, hipMemcpyDeviceToDevice,
                          p->stream));
@@ -791,7 +877,19 @@ static ksc_status convert(ksc_problem* p, bool to_spec, const void* src, void* d
   for (int c = 0; c < p->nc; ++c) {
     const CurveDev& d = p->cd[c];
     hipError_t e;
-    if (p->dtype == KSC_F64) {
+    if (p->odd()) {
+      if (p->dtype == KSC_F64) {
+        const double* ph = static_cast<const double*>(to_spec ? src : dst) + d.poff;
+        double* sp = static_cast<double*>(const_cast<void*>(to_spec ? dst : src)) + d.off;
+        e = to_spec ? ksc::launch_p2s_odd_f64(d.n_x, d.n_s, p->stream, ph, sp)
+                    : ksc::launch_s2p_odd_f64(d.n_x, d.n_s, p->stream, sp, const_cast<double*>(ph));
+      } else {
+        const float* ph = static_cast<const float*>(to_spec ? src : dst) + d.poff;
+        float* sp = static_cast<float*>(const_cast<void*>(to_spec ? dst : src)) + d.off;
+        e = to_spec ? ksc::launch_p2s_odd_f32(d.n_x, d.n_s, p->stream, ph, sp)
+                    : ksc::launch_s2p_odd_f32(d.n_x, d.n_s, p->stream, sp, const_cast<float*>(ph));
+      }
+    } else if (p->dtype == KSC_F64) {
       const double* ph = static_cast<const double*>(to_spec ? src : dst) + d.poff;
       cplx<double>* sp = reinterpret_cast<cplx<double>*>(const_cast<void*>(to_spec ? dst : src)) + d.off;
       e = to_spec ? ksc::launch_p2s_f64(d.n_x, d.n_s, p->stream, ph, sp)
@@ -878,8 +976,7 @@ ksc_status ksc_descend(ksc_problem* p, void* state, void* scratch, int64_t n_ste
   ksc_status st = ensure_pre(p, dtau, p->stream);
   if (st != KSC_OK) return st;
   // the endpoint rows of scratch must match the state's: copy the whole state once
-  KSC_HIP(hipMemcpyAsync(scratch, state, size_t(2 * p->numel_c) * p->esize(),
-                         hipMemcpyDeviceToDevice, p->stream));
+  KSC_HIP(hipMemcpyAsync(scratch, state, p->state_bytes(), hipMemcpyDeviceToDevice, p->stream));
   // groups of `every` steps; an odd group ends in scratch and is copied back
   const int G = every;
   const ksc_problem::Key want{state, scratch, dtau, G, active, p->W, p->policy, p->stream};
@@ -897,8 +994,8 @@ ksc_status ksc_descend(ksc_problem* p, void* state, void* scratch, int64_t n_ste
   for (int64_t gi = 0; gi < groups; ++gi) {
     KSC_HIP(hipGraphLaunch(p->gexec, p->stream));
     if (G % 2 == 1)
-      KSC_HIP(hipMemcpyAsync(state, scratch, size_t(2 * p->numel_c) * p->esize(),
-                             hipMemcpyDeviceToDevice, p->stream));
+      KSC_HIP(hipMemcpyAsync(state, scratch, p->state_bytes(), hipMemcpyDeviceToDevice,
+                             p->stream));
     if (J2_trace)
       KSC_HIP(hipMemcpyAsync(J2_trace + gi * p->nc, p->d_J2, p->nc * sizeof(double),
                              hipMemcpyDeviceToDevice, p->stream));
@@ -910,8 +1007,7 @@ ksc_status ksc_descend(ksc_problem* p, void* state, void* scratch, int64_t n_ste
     if (st != KSC_OK) return st;
   }
   if (rem % 2 == 1)
-    KSC_HIP(hipMemcpyAsync(state, scratch, size_t(2 * p->numel_c) * p->esize(),
-                           hipMemcpyDeviceToDevice, p->stream));
+    KSC_HIP(hipMemcpyAsync(state, scratch, p->state_bytes(), hipMemcpyDeviceToDevice, p->stream));
   return KSC_OK;
 }
 
@@ -992,6 +1088,7 @@ ksc_status ksc_tune(ksc_problem* p, const char* cache_path) {
   hipRuntimeGetVersion(&rt);
   std::ostringstream key;
   key << prop.gcnArchName << "|" << rt << "|" << (p->dtype == KSC_F64 ? "f64" : "f32") << "|";
+  if (p->odd()) key << "odd|";
   for (const auto& d : p->desc) key << d.n_x << "x" << d.n_s << ";";
   std::string kstr = key.str();
   // a long key is hashed to keep the file small
@@ -1015,7 +1112,7 @@ ksc_status ksc_tune(ksc_problem* p, const char* cache_path) {
       }
     }
   }
-  const size_t bytes = size_t(2 * p->numel_c) * p->esize();
+  const size_t bytes = p->state_bytes();
   void *x = nullptr, *g = nullptr;
   double* j2 = nullptr;
   KSC_HIP(hipMalloc(&x, bytes));

@@ -115,10 +115,35 @@ __device__ __forceinline__ void store_wave_partials(double a, double b, double c
   }
 }
 
-// 16-byte vector of the state type (two FP32 complex values or one FP64).
+// 16-byte vector of the state's scalar type (four FP32 or two FP64 values).
 template <typename T>
 struct alignas(16) vec16 {
   T v[4 / (sizeof(T) / 4)];
+};
+
+// State elements as seen by the staging copies: a complex Fourier
+// coefficient (full space) or one real coefficient (odd subspace), held in a
+// 16-byte chunk of scalars.
+template <typename V>
+struct elem {
+  using S = V;
+  static constexpr int n = 1;  // scalars per element
+  __device__ __forceinline__ static void put(vec16<S>& w, int h, V x) { w.v[h] = x; }
+  __device__ __forceinline__ static V get(const vec16<S>& w, int h) { return w.v[h]; }
+  __device__ __forceinline__ static V zero() { return V(0); }
+};
+template <typename T>
+struct elem<cplx<T>> {
+  using S = T;
+  static constexpr int n = 2;
+  __device__ __forceinline__ static void put(vec16<S>& w, int h, cplx<T> x) {
+    w.v[2 * h] = x.r;
+    w.v[2 * h + 1] = x.i;
+  }
+  __device__ __forceinline__ static cplx<T> get(const vec16<S>& w, int h) {
+    return cplx<T>{w.v[2 * h], w.v[2 * h + 1]};
+  }
+  __device__ __forceinline__ static cplx<T> zero() { return cplx<T>{T(0), T(0)}; }
 };
 
 // Copy the contiguous complex range [G_lo, G_hi) of global memory `g` into LDS
@@ -126,11 +151,12 @@ struct alignas(16) vec16 {
 // the n elements starting at buf[0] is zero-filled.  `base - shift` is
 // 16-byte aligned, so whole 16-byte chunks move with one load and one LDS
 // store; a chunk straddling the valid range is moved element by element.
-template <typename T, int NT, int NMAX>
-__device__ __forceinline__ void stage_block(cplx<T>* __restrict__ buf, const cplx<T>* __restrict__ g,
+template <typename V, int NT, int NMAX>
+__device__ __forceinline__ void stage_block(V* __restrict__ buf, const V* __restrict__ g,
                                             long long base, int shift, int n, long long G_lo,
                                             long long G_hi) {
-  constexpr int E = 16 / int(sizeof(cplx<T>));  // complex values per chunk
+  using T = typename elem<V>::S;
+  constexpr int E = 16 / int(sizeof(V));  // elements per chunk
   constexpr int NQ = (NMAX + E * NT - 1) / (E * NT);  // chunks per thread, at most
   const long long G0 = base - shift;             // global index of buf[0]
   const int nq = (n + E - 1) / E;
@@ -149,9 +175,7 @@ __device__ __forceinline__ void stage_block(cplx<T>* __restrict__ buf, const cpl
 #pragma unroll
       for (int h = 0; h < E; ++h) {
         const bool ok = q < nq && (G + h >= G_lo) && (G + h < G_hi);
-        const cplx<T> x = ok ? g[G + h] : cplx<T>{T(0), T(0)};
-        w[i].v[2 * h] = x.r;
-        w[i].v[2 * h + 1] = x.i;
+        elem<V>::put(w[i], h, ok ? g[G + h] : elem<V>::zero());
       }
     }
   }
@@ -168,12 +192,12 @@ __device__ __forceinline__ void stage_block(cplx<T>* __restrict__ buf, const cpl
 // element by element so no row outside [G_lo, G_hi) is touched.  A thread's
 // chunks go in groups of GB: every read of a group (LDS, and global with ADD)
 // is issued before its first store, so their latencies overlap.
-template <typename T, int NT, int NMAX, bool ADD>
-__device__ __forceinline__ void flush_block(cplx<T>* __restrict__ gout,
-                                            const cplx<T>* __restrict__ gin,
-                                            const cplx<T>* __restrict__ buf, long long base,
+template <typename V, int NT, int NMAX, bool ADD>
+__device__ __forceinline__ void flush_block(V* __restrict__ gout, const V* __restrict__ gin,
+                                            const V* __restrict__ buf, long long base,
                                             int shift, int n, long long G_lo, long long G_hi) {
-  constexpr int E = 16 / int(sizeof(cplx<T>));
+  using T = typename elem<V>::S;
+  constexpr int E = 16 / int(sizeof(V));
   constexpr int NQ = (NMAX + E * NT - 1) / (E * NT);  // chunks per thread, at most
   constexpr int GB = 8;
   const long long G0 = base - shift;
@@ -200,16 +224,14 @@ __device__ __forceinline__ void flush_block(cplx<T>* __restrict__ gout,
 #pragma unroll
           for (int h = 0; h < E; ++h) {
             const bool ok = q < nq && (G + h >= G_lo) && (G + h < G_hi);
-            const cplx<T> y = ok ? gin[G + h] : cplx<T>{T(0), T(0)};
-            x[i].v[2 * h] = y.r;
-            x[i].v[2 * h + 1] = y.i;
+            elem<V>::put(x[i], h, ok ? gin[G + h] : elem<V>::zero());
           }
         }
       }
 #pragma unroll
       for (int i = 0; i < GB; ++i)
 #pragma unroll
-        for (int h = 0; h < 2 * E; ++h) w[i].v[h] += x[i].v[h];
+        for (int h = 0; h < E * elem<V>::n; ++h) w[i].v[h] += x[i].v[h];
     }
 #pragma unroll
     for (int i = 0; i < GB; ++i) {
@@ -223,7 +245,7 @@ __device__ __forceinline__ void flush_block(cplx<T>* __restrict__ gout,
       } else if (q < nq) {
 #pragma unroll
         for (int h = 0; h < E; ++h)
-          if (G + h >= G_lo && G + h < G_hi) gout[G + h] = cplx<T>{w[i].v[2 * h], w[i].v[2 * h + 1]};
+          if (G + h >= G_lo && G + h < G_hi) gout[G + h] = elem<V>::get(w[i], h);
       }
     }
   }
@@ -247,7 +269,7 @@ __device__ __forceinline__ void tile_body(const KernelArgs<T>& a, const CurveDev
   const long long base = cd.off + (long long)(j0 - 1) * KM;
   const int sh = int(((base % E) + E) % E);
   __syncthreads();  // the previous tile of a persistent workgroup is done with the LDS
-  stage_block<T, ROWS, BR * KM + E>(buf, a.in, base, sh, BR * KM + sh,
+  stage_block<cplx<T>, ROWS, BR * KM + E>(buf, a.in, base, sh, BR * KM + sh,
                        cd.off + (long long)(j0 > 0 ? j0 - 1 : 0) * KM,
                        cd.off + (long long)min(n_s, j0 + ROWS + 1) * KM);
   __syncthreads();
@@ -460,7 +482,7 @@ __device__ __forceinline__ void tile_body(const KernelArgs<T>& a, const CurveDev
       });
     }
     __syncthreads();
-    flush_block<T, ROWS, ROWS * KM + E, MODE == MODE_STEP>(a.out, a.in, buf, obase, osh, ROWS * KM + osh, obase,
+    flush_block<cplx<T>, ROWS, ROWS * KM + E, MODE == MODE_STEP>(a.out, a.in, buf, obase, osh, ROWS * KM + osh, obase,
                                             cd.off + (long long)min(n_s, j0 + ROWS) * KM);
   }
 }
@@ -496,7 +518,7 @@ __device__ __forceinline__ void tile_body2(const KernelArgs<T>& a, const CurveDe
   const long long base = cd.off + (long long)(j0 - 1) * KM;
   const int sh = int(((base % E) + E) % E);
   __syncthreads();
-  stage_block<T, NT, BR * KM + E>(buf, a.in, base, sh, BR * KM + sh,
+  stage_block<cplx<T>, NT, BR * KM + E>(buf, a.in, base, sh, BR * KM + sh,
                                   cd.off + (long long)(j0 > 0 ? j0 - 1 : 0) * KM,
                                   cd.off + (long long)min(n_s, j0 + ROWS + 1) * KM);
   __syncthreads();
@@ -710,7 +732,7 @@ __device__ __forceinline__ void tile_body2(const KernelArgs<T>& a, const CurveDe
       });
     }
     __syncthreads();
-    flush_block<T, NT, ROWS * KM + E, MODE == MODE_STEP>(a.out, a.in, buf, obase, osh, ROWS * KM + osh, obase,
+    flush_block<cplx<T>, NT, ROWS * KM + E, MODE == MODE_STEP>(a.out, a.in, buf, obase, osh, ROWS * KM + osh, obase,
                                           cd.off + (long long)min(n_s, j0 + ROWS) * KM);
   }
 }

@@ -80,7 +80,8 @@ class GpuBackend:
     def promote(self) -> "GpuBackend":
         """The same curves continued in FP64."""
         from .problem import Problem
-        p64 = Problem(self.prob.curves, dtype=self._torch.float64, device=self.state.device)
+        p64 = Problem(self.prob.curves, dtype=self._torch.float64, device=self.state.device,
+                      space=self.prob.space)
         b = GpuBackend(p64, self.state.double())
         b.active.copy_(self.active)
         return b

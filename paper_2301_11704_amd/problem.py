@@ -51,21 +51,29 @@ def _ptr(t: torch.Tensor | None) -> int | None:
 class Problem:
     """A batch of curves sharing one dtype (torch.float32 or torch.float64).
 
-    States are flat device tensors of ``numel`` scalars (curve-major, row-major,
-    interleaved re/im); ``view(state, c)`` gives curve c as [n_s, K+1, 2].
+    space="full": states are flat device tensors of ``numel`` scalars
+    (curve-major, row-major, interleaved re/im); ``view(state, c)`` gives curve
+    c as [n_s, K+1, 2].
+    space="odd" (inversion-symmetric subspace, u_hat_k = i b_k): rows of the K
+    reals b_1..b_K; ``view(state, c)`` gives [n_s, K].
     """
 
-    def __init__(self, curves, dtype=torch.float32, device="cuda"):
+    def __init__(self, curves, dtype=torch.float32, device="cuda", space="full"):
         self.curves = [c if isinstance(c, CurveDesc) else CurveDesc(**c) for c in curves]
         if dtype not in (torch.float32, torch.float64):
             raise ValueError("dtype must be torch.float32 or torch.float64")
+        spaces = {"full": _lib.KSC_SPACE_FULL, "odd": _lib.KSC_SPACE_ODD}
+        if space not in spaces:
+            raise ValueError("space must be 'full' or 'odd'")
+        self.space = space
         self.dtype = dtype
         self.device = torch.device(device)
         arr = (_lib.CurveDescC * len(self.curves))(*[c.to_c() for c in self.curves])
         h = ctypes.c_void_p()
         dt = _lib.KSC_F64 if dtype == torch.float64 else _lib.KSC_F32
         with torch.cuda.device(self.device):
-            check(lib().ksc_create(arr, len(self.curves), dt, self._stream(), ctypes.byref(h)))
+            check(lib().ksc_create2(arr, len(self.curves), dt, spaces[space], self._stream(),
+                                    ctypes.byref(h)))
         self._h = h
         L = lib()
         self.numel = int(L.ksc_state_numel(h))
@@ -111,17 +119,28 @@ class Problem:
 
     def view(self, state: torch.Tensor, c: int) -> torch.Tensor:
         cd = self.curves[c]
+        if self.space == "odd":
+            n = cd.n_s * (self.modes[c] - 1)
+            return state[self.offsets[c]:self.offsets[c] + n].view(cd.n_s, self.modes[c] - 1)
         n = cd.n_s * self.modes[c] * 2
         return state[self.offsets[c]:self.offsets[c] + n].view(cd.n_s, self.modes[c], 2)
 
     def upload(self, state: torch.Tensor, c: int, U: np.ndarray) -> None:
-        """Copy complex host coefficients [n_s, K+1] of curve c into the state."""
+        """Copy host coefficients of curve c into the state: complex [n_s, K+1]
+        (full space) or real b [n_s, K] (odd subspace)."""
         U = np.asarray(U)
-        v = np.stack([U.real, U.imag], axis=-1)
+        if self.space == "odd":
+            if np.iscomplexobj(U):
+                raise ValueError("the odd subspace takes the real coefficients b [n_s, K]")
+            v = U
+        else:
+            v = np.stack([U.real, U.imag], axis=-1)
         self.view(state, c).copy_(torch.from_numpy(np.ascontiguousarray(v)).to(self.dtype))
 
     def download(self, state: torch.Tensor, c: int) -> np.ndarray:
         v = self.view(state, c).detach().double().cpu().numpy()
+        if self.space == "odd":
+            return v
         return v[..., 0] + 1j * v[..., 1]
 
     # -- the C ABI calls ----------------------------------------------------

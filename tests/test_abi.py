@@ -77,3 +77,25 @@ def test_create_validates_before_touching_the_device():
     assert b"scale" in L.ksc_last_error()
     assert create(n_x=48) == -3 and b"n_x=48" in L.ksc_last_error()
     assert out.value is None
+
+
+def test_create2_validates_the_state_space():
+    """ksc_create2: an unknown state space is an argument error; the
+    inversion-symmetric subspace in FP64 stops at n_x = 128 (one lane per row);
+    both are reported before any HIP call."""
+    from paper_2301_11704_amd import _lib
+    if not os.path.exists(_lib.LIB_PATH):
+        pytest.skip("libksc.so not built")
+    L = _lib.lib()
+    out = ctypes.c_void_p()
+
+    def create2(space, dtype, n_x=32):
+        arr = (_lib.CurveDescC * 1)(_lib.CurveDescC(64, n_x, 22.0, 0, 40.0, 0.0))
+        return L.ksc_create2(arr, 1, dtype, space, None, ctypes.byref(out))
+
+    assert create2(2, 0) == -1 and b"space" in L.ksc_last_error()
+    assert create2(-1, 1) == -1
+    assert create2(_lib.KSC_SPACE_ODD, _lib.KSC_F64, 256) == -3
+    assert b"n_x <= 128" in L.ksc_last_error()
+    assert create2(_lib.KSC_SPACE_ODD, _lib.KSC_F64, 48) == -3
+    assert out.value is None
