@@ -23,7 +23,10 @@ Discretization choices where the paper leaves room (each is a stated reading):
     g = d sigma / d s = sin^2(theta) / (pi S) is the diagonal factor of the
     paper's differentiation matrix (eq. rational_diff_matrix).  The finite map
     s = T sigma has g = 1/T.
-  * d/ds of a row quantity q is g_j (q_{j+1} - q_{j-1}) / (2 dsigma).
+  * d/ds of a row quantity q is g_j (q_{j+1} - q_{j-1}) / (2 dsigma)
+    (ds = "stencil"), or the paper's rational Chebyshev differentiation matrix
+    D_t applied along s (ds = "spectral", rational map only; Sec. IV,
+    eq. rational_diff_matrix).
   * int ds is the trapezoid rule in sigma with weights w_j = dsigma / g_j over
     the interior rows; r and G vanish on the two end rows (Sec. V.C.1).
 """
@@ -46,9 +49,14 @@ class Curve:
     """
 
     def __init__(self, n_s: int, n_x: int, L: float, map: str = "rational",
-                 scale: float = 40.0, s0: float = 0.0):
+                 scale: float = 40.0, s0: float = 0.0, ds: str = "stencil"):
         if n_s < 3:
             raise ValueError("need at least 3 rows")
+        if ds not in ("stencil", "spectral"):
+            raise ValueError(ds)
+        if ds == "spectral" and map != "rational":
+            raise ValueError("the spectral d/ds is the rational Chebyshev one (rational map)")
+        self.ds = ds
         self.n_s, self.n_x, self.L = int(n_s), int(n_x), float(L)
         self.map, self.scale, self.s0 = map, float(scale), float(s0)
         self.K = (self.n_x - 1) // 3
@@ -76,6 +84,10 @@ class Curve:
             raise ValueError(map)
         self.w = np.zeros(self.n_s)
         self.w[1:-1] = self.dsigma / self.g[1:-1]
+        if ds == "spectral":
+            # the paper's D_t numbers its points from s = +inf; rows here run
+            # from s = -inf, so both indices are reversed
+            self.D = rational_Dt(self.n_s - 2, self.scale)[::-1, ::-1].copy()
 
     @property
     def shape(self):
@@ -158,9 +170,30 @@ def _dxxxx(c: Curve, Uh: np.ndarray) -> np.ndarray:
 
 
 def _ds(c: Curve, Q: np.ndarray) -> np.ndarray:
-    """d/ds on interior rows: g_j (q_{j+1} - q_{j-1}) / (2 dsigma); zero on end rows."""
+    """d/ds on interior rows: g_j (q_{j+1} - q_{j-1}) / (2 dsigma), or D_t q for
+    the spectral variant; zero on end rows."""
     out = np.zeros_like(Q)
+    if c.ds == "spectral":
+        out[1:-1] = (c.D @ Q)[1:-1]
+        return out
     out[1:-1] = c.g[1:-1, None] * (Q[2:] - Q[:-2]) / (2.0 * c.dsigma)
+    return out
+
+
+def _ds_adjoint(c: Curve, R: np.ndarray) -> np.ndarray:
+    """The s-part of L^dagger: the adjoint of -d/ds in the inner product <p, q>
+    (weights w_j on the interior rows) applied to r, zero on the end rows.
+
+    Stencil: this is +g_j (r_{j+1} - r_{j-1}) / (2 dsigma), the paper's r_s (the
+    discrete and the continuous adjoint coincide for the central difference
+    with trapezoid weights).  Spectral: -(1/w_i) sum_j D_t[j, i] w_j r_j, the
+    exact discrete adjoint of -D_t; it agrees with D_t r up to the quadrature
+    error of the trapezoid rule.
+    """
+    if c.ds == "stencil":
+        return _ds(c, R)
+    out = np.zeros_like(R)
+    out[1:-1] = -(c.D.T @ (c.w[:, None] * R))[1:-1] / c.w[1:-1, None]
     return out
 
 
@@ -224,6 +257,13 @@ def J_arc(c: Curve, U: np.ndarray) -> float:
     """
     U = _clean(c, U)
     R = residual(c, U)
+    if c.ds == "spectral":
+        # |u_s| ds = |D_t u|_j w_j on the interior rows
+        Us = _ds(c, U)
+        a = _row_norm(c, R)[1:-1]
+        b = _row_norm(c, Us)[1:-1] * c.w[1:-1]
+        den = b.sum()
+        return float((a * b).sum() / den) if den > 0 else float("nan")
     Dsig = np.zeros_like(U)
     Dsig[1:-1] = (U[2:] - U[:-2]) / (2.0 * c.dsigma)
     a = _row_norm(c, R)[1:-1]
@@ -267,7 +307,7 @@ def adjoint(c: Curve, U: np.ndarray, R: np.ndarray | None = None) -> np.ndarray:
         R = residual(c, U)
     u = to_physical(U, c.n_x)
     rx = to_physical(_dx(c, R), c.n_x)
-    out = _ds(c, R) + to_spectral(u * rx, c.K) - _dxx(c, R) - _dxxxx(c, R)
+    out = _ds_adjoint(c, R) + to_spectral(u * rx, c.K) - _dxx(c, R) - _dxxxx(c, R)
     out[0] = 0.0
     out[-1] = 0.0
     return out
@@ -329,18 +369,20 @@ def rational_Dt(M: int, S: float) -> np.ndarray:
     """D_t of eq. rational_diff_matrix on the M+2 rational Chebyshev points
     s_j = s0 + S cot(j pi / (M+1)) (eq. t_grid; j = 0 is s = +inf).
 
-    Used only as a reference operator in the metric test.
+    Used by the metric test and as the spectral d/ds of ``Curve(ds="spectral")``.
     """
     n = M + 2
     cb = np.ones(n)
     cb[0] = cb[-1] = 2.0
-    j = np.arange(n)[:, None, None]
-    m = np.arange(n)[None, :, None]
-    k = np.arange(n)[None, None, :]
+    idx = np.arange(n)
     h = np.pi / (M + 1)
-    terms = k / (cb[None, :, None] * cb[None, None, :]) * np.cos(m * k * h) * np.sin(k * j * h)
-    D = terms.sum(axis=2)
-    D *= (2.0 / (S * (M + 1))) * np.sin(np.arange(n) * h)[:, None] ** 2
+    # angles k j h reduced exactly modulo 2 pi (integer arithmetic) before sin/cos
+    ph = (np.outer(idx, idx) % (2 * (M + 1))) * h
+    sin_jk = np.sin(ph)                     # [j, k]: sin(k j h)
+    cos_mk = np.cos(ph)                     # [m, k]: cos(m k h)
+    # D[j, m] = sum_k (k / (cbar_m cbar_k)) cos(m k h) sin(k j h), as one matrix product
+    D = (sin_jk * (idx / cb)[None, :]) @ cos_mk.T / cb[None, :]
+    D *= (2.0 / (S * (M + 1))) * np.sin(idx * h)[:, None] ** 2
     return D
 
 # ----------------------------------------------------------------------------

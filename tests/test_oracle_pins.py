@@ -453,3 +453,101 @@ def test_odd_gradient_is_the_derivative_in_b():
     rich = (4 * fd(1e-3) - fd(2e-3)) / 3
     dot = float(np.sum(G * V))
     assert abs(rich - dot) <= 1e-9 * abs(dot)
+
+
+# ------------------------------------------- spectral d/ds (paper's D_t) ---
+
+def _decaying_curve(s, n_x):
+    """A smooth curve u(x, s) that decays to u = 0 at both ends, with its exact
+    s-derivative: u_hat_1 = 0.3 sech(s/4), u_hat_2 = -0.2 i sech(s/4) tanh(s/4)."""
+    K1 = oracle.n_modes(n_x)
+    sech, th = 1.0 / np.cosh(s / 4.0), np.tanh(s / 4.0)
+    U = np.zeros((len(s), K1), dtype=np.complex128)
+    dU = np.zeros_like(U)
+    U[:, 1] = 0.3 * sech
+    dU[:, 1] = -0.3 * th * sech / 4.0
+    U[:, 2] = -0.2j * sech * th
+    dU[:, 2] = -0.2j * (sech ** 3 - th ** 2 * sech) / 4.0
+    return U, dU
+
+
+def test_spectral_ds_residual_converges_spectrally():
+    """With the paper's D_t along s (eq. rational_diff_matrix) the discrete
+    residual of a smooth curve matches f(u) - u_s at the collocation points with
+    an error that falls faster than any power of N_s; the central difference
+    converges at second order.  A wrong sign, orientation or scale of D_t would
+    leave an O(|u_s|) = O(5e-2) error."""
+    errs = {"spectral": [], "stencil": []}
+    for n_s in (33, 65, 129):
+        for ds in errs:
+            c = Curve(n_s, 16, 22.0, "rational", 8.0, ds=ds)
+            s = np.where(np.isinf(c.s), 0.0, c.s)
+            U, dU = _decaying_curve(s, c.n_x)
+            U[0] = U[-1] = 0.0  # the asymptotic states (u = 0)
+            R = oracle.residual(c, U)
+            exact = oracle.vector_field(c, U) - dU
+            errs[ds].append(np.abs(R[1:-1] - exact[1:-1]).max())
+    sp, st = errs["spectral"], errs["stencil"]
+    assert sp[0] < 1e-5 and sp[2] < 1e-10, sp
+    assert sp[0] / sp[1] > 100 and sp[1] / sp[2] > 100, sp
+    orders = np.log2(np.array(st[:-1]) / np.array(st[1:]))
+    assert np.all((orders > 1.8) & (orders < 2.2)), st
+
+
+def test_spectral_adjoint_identity_and_gradient():
+    """<L(u; v), r> = <v, L^dagger(u; r)> with the spectral d/ds (its s-part is
+    the weighted transpose of D_t), and the gradient equals Richardson central
+    differences of the quartic J^2 in every free coordinate."""
+    rng = np.random.default_rng(15)
+    c = Curve(14, 16, 22.0, "rational", 6.0, ds="spectral")
+    U = _rand_state(c, rng)
+    V = _rand_interior(c, rng)
+    R = _rand_interior(c, rng)
+    lhs = oracle.inner(c, oracle.jvp(c, U, V), R)
+    rhs = oracle.inner(c, V, oracle.adjoint(c, U, R))
+    assert abs(lhs - rhs) <= 1e-12 * max(abs(lhs), 1.0)
+    c = Curve(7, 8, 22.0, "rational", 6.0, ds="spectral")
+    U = _rand_state(c, rng, amp=0.5)
+    G = oracle.grad(c, U)
+    scale = np.abs(G).max()
+    eps = 1e-3
+    for j in range(1, c.n_s - 1):
+        for k in range(c.K + 1):
+            for part in (1.0, 1j):
+                if k == 0 and part == 1j:
+                    continue
+                E = np.zeros(c.shape, dtype=np.complex128)
+                E[j, k] = part
+
+                def cd(h):
+                    return (oracle.J2(c, U + h * E) - oracle.J2(c, U - h * E)) / (2 * h)
+                fd = (4 * cd(eps / 2) - cd(eps)) / 3
+                got = G[j, k].real if part == 1.0 else G[j, k].imag
+                assert abs(fd - got) <= 1e-9 * scale, (j, k, part, fd, got)
+    assert np.all(G[0] == 0) and np.all(G[-1] == 0)
+
+
+def test_spectral_step_rate_and_transpose_matches_paper_adjoint():
+    """The step decreases J^2 at the rate 2 <L^dagger r, G>; and the discrete
+    adjoint's s-part, -(1/w) D_t^T (w r), agrees with the paper's r_s = D_t r up
+    to the trapezoid rule's error, which vanishes spectrally for a smooth r
+    that decays at both ends."""
+    rng = np.random.default_rng(16)
+    c = Curve(40, 16, 22.0, "rational", 8.0, ds="spectral")
+    U = _rand_state(c, rng, amp=0.2, kmax=3)
+    J0 = oracle.J2(c, U)
+    Ad = oracle.adjoint(c, U)
+    for dtau in (1e-6, 1e-7):
+        U1 = oracle.step(c, U, dtau)
+        rate = (oracle.J2(c, U1) - J0) / dtau
+        pred = -2 * oracle.inner(c, Ad, Ad / (1 + dtau * c.A[None, :] ** 2))
+        assert abs(rate / pred - 1) < 1e-3
+    from oracle.ks import _ds, _ds_adjoint
+    errs = []
+    for n_s in (33, 65, 129):
+        c = Curve(n_s, 16, 22.0, "rational", 8.0, ds="spectral")
+        s = np.where(np.isinf(c.s), 0.0, c.s)
+        Rr, _ = _decaying_curve(s, c.n_x)
+        Rr[0] = Rr[-1] = 0.0
+        errs.append(np.abs(_ds_adjoint(c, Rr) - _ds(c, Rr))[1:-1].max())
+    assert errs[-1] < 1e-8 and errs[0] / errs[1] > 30, errs
