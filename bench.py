@@ -39,6 +39,8 @@ HBM_PEAK_GBS = 8000.0
 # FP32 or FP64 FMA per lane per clock, 256 CUs x 4 SIMDs x 16 lanes x 2 flop
 # x 2.4 GHz.
 ALU_PEAK_TFLOPS = 78.6
+# Dense FP64 matrix-core peak: the products along s run in FP64 for both dtypes.
+MFMA_F64_PEAK_TFLOPS = 78.6
 
 
 def flops_per_row(n_x: int) -> float:
@@ -110,6 +112,10 @@ def _specs_and_states(workload: str):
     if workload == "c4":
         specs, Us = ksinputs.config4_curves(64)
         return specs, Us, "finite"
+    if workload == "p22":
+        specs = ksinputs.paper_shape_specs(64)
+        Us = [ksinputs.make_curve(s, (s.n_x - 1) // 3 + 1)[2] for s in specs]
+        return specs, Us, "rational"
     cfg = {"c1": 1, "c2": 2, "c3": 3}[workload]
     specs = ksinputs.config_specs(cfg)
     Us = []
@@ -128,6 +134,8 @@ def _describe(workload, specs, space="full"):
             "c1": "1 KS curve, L=39, N_x=64, N_s=512",
             "c2": "1 KS curve, L=100, N_x=256, N_s=8192",
             "c3": "256 uneven KS curves, N_x in {32,64,128}, N_s in [128,2048]",
+            "p22": "64 KS curves with the paper's E1->E2 discretization: L=22, N_x=64, "
+                   "N_s=552 (M=550), rational map S=55",
         }[workload],
         "curves": len(specs),
         "n_x": nx if len(nx) > 1 else nx[0],
@@ -210,6 +218,51 @@ def cpu_baseline(specs, Us, budget_s=12.0, single_s=6.0):
     }
 
 
+def spectral_gemm_flops(specs, n_products):
+    """Flops of the dense D_t products along s: 2 N_s^2 2(K+1) per curve each."""
+    return n_products * sum(2.0 * s.n_s * s.n_s * 2 * ((s.n_x - 1) // 3 + 1) for s in specs)
+
+
+def spectral_leg(ksc, torch, tdt, esz, args, stream):
+    """J + gradient with the paper's spectral d/ds (dense D_t on matrix cores)
+    on the paper-shape batch: time per evaluation and the MFMA fraction of the
+    two products over the whole evaluation window (per-kernel durations are in
+    the kernel-trace profile)."""
+    specs, Us, _ = _specs_and_states("p22")
+    descs = [ksc.CurveDesc(s.n_s, s.n_x, s.L, s.map, s.scale, s.s0) for s in specs]
+    ps = ksc.Problem(descs, dtype=tdt, ds="spectral")
+    Xs = ps.new_state()
+    for c, U in enumerate(Us):
+        ps.upload(Xs, c, U)
+    Gs = torch.empty_like(Xs)
+    ps.tune(None if args.retune else args.tune_cache)
+    pol, w = ps.launch
+
+    def f():
+        ps.eval_grad(Xs, Gs)
+
+    for _ in range(args.warmup):
+        f()
+    ms = _time(torch, f, args.steps, stream)
+    ps.set_timing(True)
+    _time(torch, f, args.steps, stream)
+    fs, qs, ns = ps.read_timing()
+    ps.set_timing(False)
+    win = fs / ns
+    gf = spectral_gemm_flops(specs, 2)
+    peak = MFMA_F64_PEAK_TFLOPS
+    pts = sum(s.n_s - 2 for s in specs)
+    res = {
+        "workload": _describe("p22", specs)["workload"], "ms_per_step": ms,
+        "curve_points_per_s": pts / (ms * 1e-3), "window_ms": win, "post_kernel_ms": qs / ns,
+        "launch": {"policy": pol, "waves_per_tile": w},
+        "mfma": {"gemm_flops_per_eval": gf, "achieved_over_window": gf / (win * 1e-3) / 1e12,
+                 "peak": peak, "unit": "TFLOP/s", "frac": gf / (win * 1e-3) / 1e12 / peak},
+    }
+    del Xs, Gs, ps
+    return res
+
+
 def _alg_per_launch(specs, esz, space):
     """Algorithmic bytes (read the state, write the gradient) and flops of one
     J + gradient launch over the batch."""
@@ -263,12 +316,14 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--workload", default="c4", choices=["c4", "c1", "c2", "c3"])
+    ap.add_argument("--workload", default="c4", choices=["c4", "c1", "c2", "c3", "p22"])
     ap.add_argument("--no-cpu", action="store_true", help="skip the host oracle baseline")
     ap.add_argument("--no-extras", action="store_true", help="skip plain and streaming legs")
     ap.add_argument("--dtype", default="f32", choices=["f32", "f64"])
     ap.add_argument("--space", default="full", choices=["full", "odd"],
                     help="state space of the timed problem (odd: inversion-symmetric subspace)")
+    ap.add_argument("--ds", default="stencil", choices=["stencil", "spectral"],
+                    help="d/ds of the timed problem (spectral: the paper's D_t; rational map)")
     ap.add_argument("--tune-cache", default=TUNE_CACHE, metavar="PATH",
                     help="launch-shape cache read (or, for a shape it lacks, tuned and "
                          "appended) by the autotuner; default: the cache shipped with the package")
@@ -304,7 +359,7 @@ def main():
     esz = 8 if args.dtype == "f64" else 4
     specs, Us, _ = _specs_and_states(args.workload)
     descs = [ksc.CurveDesc(s.n_s, s.n_x, s.L, s.map, s.scale, s.s0) for s in specs]
-    prob = ksc.Problem(descs, dtype=tdt, space=args.space)
+    prob = ksc.Problem(descs, dtype=tdt, space=args.space, ds=args.ds)
     X = prob.new_state()
     for c, U in enumerate(odd_states(Us) if args.space == "odd" else Us):
         prob.upload(X, c, U)
@@ -336,6 +391,15 @@ def main():
     tflops = alg_flops / (kernel_ms * 1e-3) / 1e12
     traffic = recorded_traffic(args.workload, args.dtype, args.space)
 
+    if args.ds == "spectral":
+        # the products along s dominate: MFMA roofline over the evaluation window
+        gf = spectral_gemm_flops(specs, 2)
+        peak = MFMA_F64_PEAK_TFLOPS
+        roof = {"bound": "mfma", "achieved": gf / (kernel_ms * 1e-3) / 1e12, "peak": peak,
+                "unit": "TFLOP/s", "frac": gf / (kernel_ms * 1e-3) / 1e12 / peak, "traffic": None,
+                "kernel": "D_t products + row kernel (window)", "kernel_ms": kernel_ms,
+                "alg_flops_per_launch": gf, "post_kernel_ms": post_kernel_ms,
+                "ms_per_step_with_events": ms_ev}
     out = {
         "metric": METRIC,
         "value": value,
@@ -349,7 +413,7 @@ def main():
         "vs_baseline": None,
         "dtype": args.dtype,
         "data": "synthetic",
-        "config": dict(info, space=args.space,
+        "config": dict(info, space=args.space, ds=args.ds,
                        launch={"policy": policy, "waves_per_tile": waves,
                                "tuned": "now" if args.retune else "cache"}),
         # The fused kernel's arithmetic intensity (~15 flop/B at n_x = 128) is
@@ -367,6 +431,8 @@ def main():
             "grid_point_evals_per_s": sum((s.n_s - 2) * s.n_x for s in specs) / (ms * 1e-3),
         },
     }
+    if args.ds == "spectral":
+        out["roofline"] = roof
 
     if not args.no_extras:
         # plain: one non-persistent launch per curve and step
@@ -403,7 +469,10 @@ def main():
                            "GBs_vs_method_minimum": alg_bytes / (ms_ag * 1e-3) / 1e9,
                            "GBs_vs_recompute_design": 1.5 * alg_bytes / (ms_ag * 1e-3) / 1e9}
         del Xr, Y
-        if args.space == "full" and not (args.dtype == "f64" and max(s.n_x for s in specs) > 128):
+        if args.ds == "stencil" and args.dtype == "f32":
+            out["spectral_ds"] = spectral_leg(ksc, torch, tdt, esz, args, stream)
+        if args.space == "full" and args.ds == "stencil" and \
+                not (args.dtype == "f64" and max(s.n_x for s in specs) > 128):
             out["odd_space"] = odd_leg(ksc, torch, descs, Us, tdt, esz, specs, args, stream,
                                        kernel_ms)
         reps = STREAM_REPLICAS[args.workload] if args.replicas is None else args.replicas

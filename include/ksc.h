@@ -37,6 +37,15 @@
  *                A_k = q_k^2 - q_k^4, q_k = 2 pi k / L.
  *   J_arc        int |r| |u_s| ds / int |u_s| ds (eq. J_arc).
  *
+ * Spectral d/ds (KSC_DS_SPECTRAL, ksc_create_opts; rational map only): d/ds is
+ * the paper's rational Chebyshev differentiation matrix D_t (Sec. IV, eq.
+ * rational_diff_matrix) on the n_s points of eq. t_grid, applied along s as a
+ * dense matrix product, instead of the central difference.  The gradient is
+ * the exact gradient of the discrete J2: the s-part of L^dagger r is
+ * -(1/w_j) sum_i D_t[i][j] w_i r_i, the adjoint of -D_t in the weighted inner
+ * product (it agrees with the paper's r_s = D_t r up to quadrature error), and
+ * J_arc weights |D_t u|_j by w_j.
+ *
  * Inversion-symmetric subspace (state space KSC_SPACE_ODD, ksc_create2): the
  * fields with u(-x) = -u(x), invariant under the descent because the inversion
  * operator commutes with the residual (symmetry-preservation subsection, eq.
@@ -91,6 +100,19 @@ typedef enum {
 } ksc_space;
 
 typedef enum {
+  KSC_DS_STENCIL = 0, /* g_j (q_{j+1} - q_{j-1}) / (2 dsigma) */
+  KSC_DS_SPECTRAL = 1 /* the paper's dense D_t along s (rational map) */
+} ksc_ds;
+
+/* Creation options (ksc_create_opts). */
+typedef struct {
+  int32_t dtype;    /* ksc_dtype */
+  int32_t space;    /* ksc_space */
+  int32_t ds;       /* ksc_ds */
+  int32_t reserved; /* must be 0 */
+} ksc_options;
+
+typedef enum {
   KSC_MAP_RATIONAL = 0, /* s = s0 + scale * cot(pi (1 - sigma)); scale is the paper's S */
   KSC_MAP_FINITE = 1    /* s = scale * sigma; scale is the length T */
 } ksc_map;
@@ -126,6 +148,13 @@ ksc_status ksc_create(const ksc_curve_desc* descs, int32_t n_curves, int32_t dty
  * KSC_ERR_UNSUPPORTED for KSC_SPACE_ODD with KSC_F64 and n_x = 256. */
 ksc_status ksc_create2(const ksc_curve_desc* descs, int32_t n_curves, int32_t dtype,
                        int32_t space, void* hip_stream, ksc_problem** out);
+/* The same with every option (opts: host pointer).  KSC_DS_SPECTRAL needs the
+ * rational map on every curve, KSC_SPACE_FULL and one row per lane: n_x <= 128
+ * in FP32, n_x <= 64 in FP64, and n_s <= 16384 (KSC_ERR_UNSUPPORTED or
+ * KSC_ERR_ARG otherwise, before any device work).  It allocates D_t for every
+ * distinct n_s (n_s^2 scalars) and three state-sized work arrays. */
+ksc_status ksc_create_opts(const ksc_curve_desc* descs, int32_t n_curves, const ksc_options* opts,
+                           void* hip_stream, ksc_problem** out);
 ksc_status ksc_destroy(ksc_problem* p);
 
 /* Change the stream later calls are enqueued on. */

@@ -150,6 +150,16 @@ def config_specs(cfg: int, n_curves: int | None = None) -> list[CurveSpec]:
     raise ValueError(f"unknown workload {cfg}")
 
 
+def paper_shape_specs(n_curves: int = 64) -> list[CurveSpec]:
+    """Curves with the discretization of the paper's first KS run (L = 22,
+    N = 64 Fourier modes in x, M = 550 interior rational Chebyshev points,
+    S = 55, s0 = 0): N_x = 64, N_s = 552, rational map.  The endpoints are
+    seeded smooth states standing in for the equilibria (which the paper shows
+    only as figures); interior = blend + sin(pi sigma) perturbation."""
+    return [CurveSpec(552, 64, 22.0, 6, 1.0, 6, 0.2, True, (5, c), "rational", 55.0)
+            for c in range(n_curves)]
+
+
 def round_to(U: np.ndarray, dtype) -> np.ndarray:
     """Round complex128 data to the run precision (complex64 for FP32) and back."""
     if np.dtype(dtype) == np.float32:

@@ -15,13 +15,14 @@ STATUS_NAMES = {
 }
 KSC_F32, KSC_F64 = 0, 1
 KSC_SPACE_FULL, KSC_SPACE_ODD = 0, 1
+KSC_DS_STENCIL, KSC_DS_SPECTRAL = 0, 1
 KSC_MAP_RATIONAL, KSC_MAP_FINITE = 0, 1
 KSC_FLAG_NONFINITE, KSC_FLAG_INCREASED = 1, 2
 KSC_LAUNCH_AUTO, KSC_LAUNCH_PLAIN, KSC_LAUNCH_PERSISTENT = 0, 1, 2
 
 # Every symbol include/ksc.h declares.
 EXPORTED = (
-    "ksc_create", "ksc_create2", "ksc_destroy", "ksc_set_stream", "ksc_state_numel", "ksc_state_offset",
+    "ksc_create", "ksc_create2", "ksc_create_opts", "ksc_destroy", "ksc_set_stream", "ksc_state_numel", "ksc_state_offset",
     "ksc_phys_numel", "ksc_phys_offset", "ksc_n_modes", "ksc_set_endpoints",
     "ksc_phys_to_spec", "ksc_spec_to_phys", "ksc_eval_J", "ksc_eval_grad", "ksc_step",
     "ksc_descend", "ksc_tune", "ksc_set_launch", "ksc_get_launch", "ksc_query_flags",
@@ -46,6 +47,15 @@ class CurveDescC(ctypes.Structure):
     ]
 
 
+class OptionsC(ctypes.Structure):
+    _fields_ = [
+        ("dtype", ctypes.c_int32),
+        ("space", ctypes.c_int32),
+        ("ds", ctypes.c_int32),
+        ("reserved", ctypes.c_int32),
+    ]
+
+
 _lib = None
 
 
@@ -63,6 +73,8 @@ def lib() -> ctypes.CDLL:
     sig = {
         "ksc_create": (i32, [ctypes.POINTER(CurveDescC), i32, i32, vp, ctypes.POINTER(vp)]),
         "ksc_create2": (i32, [ctypes.POINTER(CurveDescC), i32, i32, i32, vp, ctypes.POINTER(vp)]),
+        "ksc_create_opts": (i32, [ctypes.POINTER(CurveDescC), i32, ctypes.POINTER(OptionsC), vp,
+                                  ctypes.POINTER(vp)]),
         "ksc_destroy": (i32, [vp]),
         "ksc_set_stream": (i32, [vp, vp]),
         "ksc_state_numel": (i64, [vp]),

@@ -41,6 +41,8 @@ def units():
         for nx in NXS:
             out.append((f"fused_{tname}_{nx}", "ksc_fused.hip", d + [f"-DKSC_NX={nx}"]))
             out.append((f"odd_{tname}_{nx}", "ksc_odd.hip", d + [f"-DKSC_NX={nx}"]))
+        for nx in (n for n in NXS if n * (8 if t == "double" else 4) <= 512):
+            out.append((f"spec_{tname}_{nx}", "ksc_spec.hip", d + [f"-DKSC_NX={nx}"]))
         out.append((f"mixed_{tname}", "ksc_fused.hip", d + ["-DKSC_MIXED"]))
         out.append((f"oddconv_{tname}", "ksc_odd.hip", d + ["-DKSC_ODD_CONV"]))
     return out

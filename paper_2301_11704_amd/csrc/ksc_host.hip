@@ -16,10 +16,12 @@
 #include "../../include/ksc.h"
 #include "ksc_launch.hpp"
 #include "ksc_launch_odd.hpp"
+#include "ksc_launch_spec.hpp"
 
 using ksc::cplx;
 using ksc::CurveDev;
 using ksc::KernelArgs;
+using ksc::SpecDev;
 using ksc::TileDev;
 
 namespace {
@@ -216,6 +218,7 @@ struct ksc_problem {
   int nc = 0;
   int dtype = KSC_F32;
   int space = KSC_SPACE_FULL;
+  int ds = KSC_DS_STENCIL;
   hipStream_t stream = nullptr;
   int device = 0;
   size_t lds_limit = 65536;
@@ -257,6 +260,18 @@ struct ksc_problem {
   int part_cap = 0;
   double pre_dtau = std::nan("");
 
+  // spectral d/ds: D~ = S D_t per distinct n_s, per-curve descriptors in tile
+  // order, one group of curves per n_x, and three state-sized work arrays
+  void* d_dpool = nullptr;
+  SpecDev* d_spec = nullptr;
+  struct SpecGroup {
+    int nx, first, count, max_ns;
+  };
+  std::vector<SpecGroup> spec_groups;
+  void* d_Y = nullptr;
+  void* d_WR = nullptr;
+  void* d_P = nullptr;
+
   // descent graph cache
   hipStream_t cap_stream = nullptr;
   hipGraphExec_t gexec = nullptr;
@@ -280,6 +295,7 @@ struct ksc_problem {
 
   size_t esize() const { return dtype == KSC_F64 ? 8 : 4; }
   bool odd() const { return space == KSC_SPACE_ODD; }
+  bool spectral() const { return ds == KSC_DS_SPECTRAL; }
   // bytes of one state element, elements per row of curve d, whole-state bytes
   size_t elem_bytes() const { return odd() ? esize() : 2 * esize(); }
   int row_elems(const CurveDev& d) const { return odd() ? d.km - 1 : d.km; }
@@ -298,6 +314,10 @@ int rows_per_tile(const ksc_problem* p, int W, int nx) { return 64 * W / lanes_p
 
 // LDS staging buffer of one tile: rows j0-1 .. j0+R, 16 bytes of alignment slack.
 size_t lds_for(const ksc_problem* p, int W, int nx) {
+  if (p->spectral()) {  // state rows and d/ds rows of the tile, each with slack
+    const size_t cs = 2 * p->esize(), E = 16 / cs;
+    return 2 * (size_t(rows_per_tile(p, W, nx)) * modes_of(nx) + 2 * E) * cs;
+  }
   // (odd subspace: the last 16-byte chunk of a staged block may start up to
   // 16 bytes past the block and end 16 bytes after that)
   if (p->odd()) return size_t(rows_per_tile(p, W, nx) + 2) * (modes_of(nx) - 1) * p->esize() + 32;
@@ -595,6 +615,200 @@ ksc_status launch_post(ksc_problem* p, int mode, const void* in, void* out, cons
   return KSC_OK;
 }
 
+// ------------------------------------------------------- spectral d/ds --
+
+hipError_t spec_gemm(int nx, int epi, dim3 grid, hipStream_t s, const ksc::SpecArgs<float>& a,
+                     hipEvent_t e0, hipEvent_t e1) {
+  switch (nx) {
+    case 8: return ksc::launch_spec_gemm_f32_8(epi, grid, s, a, e0, e1);
+    case 16: return ksc::launch_spec_gemm_f32_16(epi, grid, s, a, e0, e1);
+    case 32: return ksc::launch_spec_gemm_f32_32(epi, grid, s, a, e0, e1);
+    case 64: return ksc::launch_spec_gemm_f32_64(epi, grid, s, a, e0, e1);
+    case 128: return ksc::launch_spec_gemm_f32_128(epi, grid, s, a, e0, e1);
+    default: return hipErrorInvalidValue;
+  }
+}
+hipError_t spec_gemm(int nx, int epi, dim3 grid, hipStream_t s, const ksc::SpecArgs<double>& a,
+                     hipEvent_t e0, hipEvent_t e1) {
+  switch (nx) {
+    case 8: return ksc::launch_spec_gemm_f64_8(epi, grid, s, a, e0, e1);
+    case 16: return ksc::launch_spec_gemm_f64_16(epi, grid, s, a, e0, e1);
+    case 32: return ksc::launch_spec_gemm_f64_32(epi, grid, s, a, e0, e1);
+    case 64: return ksc::launch_spec_gemm_f64_64(epi, grid, s, a, e0, e1);
+    default: return hipErrorInvalidValue;
+  }
+}
+hipError_t spec_row(int nx, int W, int mode, int grid, size_t lds, hipStream_t s,
+                    const ksc::SpecRowArgs<float>& a, hipEvent_t e0, hipEvent_t e1) {
+  switch (nx) {
+    case 8: return ksc::launch_spec_row_f32_8(W, mode, grid, lds, s, a, e0, e1);
+    case 16: return ksc::launch_spec_row_f32_16(W, mode, grid, lds, s, a, e0, e1);
+    case 32: return ksc::launch_spec_row_f32_32(W, mode, grid, lds, s, a, e0, e1);
+    case 64: return ksc::launch_spec_row_f32_64(W, mode, grid, lds, s, a, e0, e1);
+    case 128: return ksc::launch_spec_row_f32_128(W, mode, grid, lds, s, a, e0, e1);
+    default: return hipErrorInvalidValue;
+  }
+}
+hipError_t spec_row(int nx, int W, int mode, int grid, size_t lds, hipStream_t s,
+                    const ksc::SpecRowArgs<double>& a, hipEvent_t e0, hipEvent_t e1) {
+  switch (nx) {
+    case 8: return ksc::launch_spec_row_f64_8(W, mode, grid, lds, s, a, e0, e1);
+    case 16: return ksc::launch_spec_row_f64_16(W, mode, grid, lds, s, a, e0, e1);
+    case 32: return ksc::launch_spec_row_f64_32(W, mode, grid, lds, s, a, e0, e1);
+    case 64: return ksc::launch_spec_row_f64_64(W, mode, grid, lds, s, a, e0, e1);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+// One evaluation with the spectral d/ds: Y = D_t U, the row kernel, and (not
+// for MODE_J) the transposed product whose epilogue writes the gradient or
+// the stepped state.  ev (nullable): start of the first launch, end of the last.
+template <typename T>
+ksc_status launch_spectral(ksc_problem* p, int mode, const void* in, void* out,
+                           const double* scale, const uint8_t* active, hipStream_t s,
+                           const hipEvent_t* ev) {
+  const int W = p->W;
+  const int ng = int(p->spec_groups.size());
+  hipEvent_t e_first = ev ? ev[0] : nullptr, e_last = ev ? ev[1] : nullptr;
+  ksc::SpecArgs<T> ga{};
+  ga.dpool = static_cast<const double*>(p->d_dpool);
+  ga.wlT = static_cast<const T*>(p->d_wlT);
+  ga.pre = static_cast<const T*>(p->d_pre);
+  ga.scale = scale;
+  ga.active = active;
+  auto grid_of = [](const ksc_problem::SpecGroup& g) {
+    return dim3((g.max_ns + ksc::kSpecRowsPerBlock - 1) / ksc::kSpecRowsPerBlock, g.count);
+  };
+  // 1. Y = D_t U
+  for (int g = 0; g < ng; ++g) {
+    const auto& G = p->spec_groups[g];
+    ksc::SpecArgs<T> a = ga;
+    a.curves = p->d_spec + G.first;
+    a.b = static_cast<const T*>(in);
+    a.out = static_cast<T*>(p->d_Y);
+    hipError_t e = spec_gemm(G.nx, ksc::EPI_Y, grid_of(G), s, a, g == 0 ? e_first : nullptr, nullptr);
+    if (e != hipSuccess) return fail(KSC_ERR_HIP, std::string("spectral product: ") + hipGetErrorString(e));
+  }
+  // 2. rows: residual, cost partials, row-local adjoint part
+  ksc::SpecRowArgs<T> ra{};
+  ra.a = make_args<T>(p, in, nullptr, scale, active);
+  ra.y = static_cast<const cplx<T>*>(p->d_Y);
+  ra.wr = static_cast<cplx<T>*>(p->d_WR);
+  ra.pl = static_cast<cplx<T>*>(p->d_P);
+  const int nt = int(p->tiles.size());
+  int t0 = 0;
+  while (t0 < nt) {
+    const int nx = p->cd[p->tiles[t0].curve].n_x;
+    int t1 = t0;
+    while (t1 < nt && p->cd[p->tiles[t1].curve].n_x == nx) ++t1;
+    ksc::SpecRowArgs<T> rg = ra;
+    rg.a.tile_base = t0;
+    rg.a.n_tiles = t1 - t0;
+    int grid = t1 - t0;
+    if (p->policy == KSC_LAUNCH_PERSISTENT) grid = std::min(grid, p->n_cu * (W == 1 ? 4 : 2));
+    const bool last = (mode == ksc::MODE_J) && t1 == nt;
+    hipError_t e = spec_row(nx, W, mode == ksc::MODE_J ? ksc::MODE_J : ksc::MODE_GRAD, grid,
+                            lds_for(p, W, nx), s, rg, nullptr, last ? e_last : nullptr);
+    if (e != hipSuccess) return fail(KSC_ERR_HIP, std::string("spectral rows: ") + hipGetErrorString(e));
+    t0 = t1;
+  }
+  if (mode == ksc::MODE_J) return KSC_OK;
+  // 3. Z' = D_t^T (2 w L r_hat) and the output
+  for (int g = 0; g < ng; ++g) {
+    const auto& G = p->spec_groups[g];
+    ksc::SpecArgs<T> a = ga;
+    a.curves = p->d_spec + G.first;
+    a.b = static_cast<const T*>(p->d_WR);
+    a.p = static_cast<const T*>(p->d_P);
+    a.u = static_cast<const T*>(in);
+    a.out = static_cast<T*>(out);
+    hipError_t e = spec_gemm(G.nx, mode == ksc::MODE_GRAD ? ksc::EPI_GRAD : ksc::EPI_STEP,
+                             grid_of(G), s, a, nullptr, g == ng - 1 ? e_last : nullptr);
+    if (e != hipSuccess) return fail(KSC_ERR_HIP, std::string("spectral product: ") + hipGetErrorString(e));
+  }
+  return KSC_OK;
+}
+
+// D~ = S D_t on n points in the row order used here (row 0 is s = -inf): the
+// derivative of the Chebyshev-Gauss-Lobatto interpolant in x = cos(theta)
+// times dx/ds = sin^3(theta) / S, i.e. D_t = diag(sin^3 theta / S) D_x with
+// D_x[i][j] = (c_i / c_j) (-1)^(i+j) / (x_i - x_j) off the diagonal
+// (c_0 = c_N = 2, else 1), the diagonal from the zero row sums, and
+// x_i - x_j = -2 sin((i+j) pi / 2N) sin((i-j) pi / 2N).  This is the closed
+// form of the sum in eq. rational_diff_matrix (the derivative of the same
+// interpolant).
+std::vector<double> make_dtilde(int n) {
+  const int N = n - 1;
+  std::vector<double> Dp(size_t(n) * n, 0.0);  // paper's numbering (i = 0: s = +inf)
+  for (int i = 0; i < n; ++i) {
+    const double ci = (i == 0 || i == N) ? 2.0 : 1.0;
+    double diag = 0.0;
+    for (int j = 0; j < n; ++j) {
+      if (j == i) continue;
+      const double cj = (j == 0 || j == N) ? 2.0 : 1.0;
+      const double dx = -2.0 * std::sin((i + j) * M_PI / (2.0 * N)) * std::sin((i - j) * M_PI / (2.0 * N));
+      const double v = (ci / cj) * (((i + j) % 2) ? -1.0 : 1.0) / dx;
+      Dp[size_t(i) * n + j] = v;
+      diag -= v;
+    }
+    Dp[size_t(i) * n + i] = diag;
+    const double sn = std::sin(i * M_PI / N);
+    const double f = sn * sn * sn;
+    for (int j = 0; j < n; ++j) Dp[size_t(i) * n + j] *= f;
+  }
+  std::vector<double> D(size_t(n) * n);
+  for (int a = 0; a < n; ++a)
+    for (int b = 0; b < n; ++b) D[size_t(a) * n + b] = Dp[size_t(N - a) * n + (N - b)];
+  return D;
+}
+
+// Matrix pool, per-curve descriptors (tile order) and work arrays.
+ksc_status setup_spectral(ksc_problem* p) {
+  std::vector<int> sizes;
+  for (const CurveDev& d : p->cd) sizes.push_back(d.n_s);
+  std::sort(sizes.begin(), sizes.end());
+  sizes.erase(std::unique(sizes.begin(), sizes.end()), sizes.end());
+  std::vector<long long> moff(sizes.size());
+  long long total = 0;
+  for (size_t i = 0; i < sizes.size(); ++i) {
+    moff[i] = total;
+    total += (long long)sizes[i] * sizes[i];
+  }
+  KSC_HIP(hipMalloc(&p->d_dpool, size_t(total) * sizeof(double)));  // FP64 for both dtypes
+  for (size_t i = 0; i < sizes.size(); ++i) {
+    std::vector<double> D = make_dtilde(sizes[i]);
+    KSC_HIP(hipMemcpy(static_cast<double*>(p->d_dpool) + moff[i], D.data(), D.size() * 8,
+                      hipMemcpyHostToDevice));
+  }
+  std::vector<SpecDev> sd;
+  p->spec_groups.clear();
+  for (int c : p->curve_order) {
+    const CurveDev& d = p->cd[c];
+    const size_t mi = std::lower_bound(sizes.begin(), sizes.end(), d.n_s) - sizes.begin();
+    SpecDev s{};
+    s.off = d.off;
+    s.dmat = moff[mi];
+    s.n_s = d.n_s;
+    s.km = d.km;
+    s.row_off = d.row_off;
+    s.mode_off = d.mode_off;
+    s.c = c;
+    s.inv_S = 1.0 / p->desc[c].scale;
+    if (p->spec_groups.empty() || p->spec_groups.back().nx != d.n_x)
+      p->spec_groups.push_back({d.n_x, int(sd.size()), 0, 0});
+    auto& G = p->spec_groups.back();
+    G.count++;
+    G.max_ns = std::max(G.max_ns, d.n_s);
+    sd.push_back(s);
+  }
+  KSC_HIP(hipMalloc(&p->d_spec, sd.size() * sizeof(SpecDev)));
+  KSC_HIP(hipMemcpy(p->d_spec, sd.data(), sd.size() * sizeof(SpecDev), hipMemcpyHostToDevice));
+  KSC_HIP(hipMalloc(&p->d_Y, p->state_bytes()));
+  KSC_HIP(hipMalloc(&p->d_WR, p->state_bytes()));
+  KSC_HIP(hipMalloc(&p->d_P, p->state_bytes()));
+  return KSC_OK;
+}
+
 constexpr size_t kMaxTimedEvals = 1 << 16;
 
 // Next event of the timing pool, or nullptr when the pool is full.
@@ -634,7 +848,20 @@ ksc_status run(ksc_problem* p, int mode, const void* in, void* out, const double
   const hipEvent_t* evf = timed ? ev : nullptr;
   const hipEvent_t* evp = timed ? ev + 2 : nullptr;
   ksc_status st;
-  if (p->dtype == KSC_F64) {
+  if (p->spectral()) {
+    // the post kernel only reduces the cost (no tile-boundary rows to finish)
+    if (p->dtype == KSC_F64) {
+      st = launch_spectral<double>(p, mode, in, out, scale, active, s, evf);
+      if (st == KSC_OK)
+        st = launch_post<double>(p, ksc::MODE_J, in, out, scale, active, J2, Jarc, track, finalize,
+                                 s, evp);
+    } else {
+      st = launch_spectral<float>(p, mode, in, out, scale, active, s, evf);
+      if (st == KSC_OK)
+        st = launch_post<float>(p, ksc::MODE_J, in, out, scale, active, J2, Jarc, track, finalize,
+                                s, evp);
+    }
+  } else if (p->dtype == KSC_F64) {
     st = launch_fused<double>(p, mode, in, out, scale, active, s, evf);
     if (st == KSC_OK)
       st = launch_post<double>(p, mode, in, out, scale, active, J2, Jarc, track, finalize, s, evp);
@@ -684,13 +911,25 @@ ksc_status ksc_create(const ksc_curve_desc* descs, int32_t n_curves, int32_t dty
 
 ksc_status ksc_create2(const ksc_curve_desc* descs, int32_t n_curves, int32_t dtype,
                        int32_t space, void* hip_stream, ksc_problem** out) {
+  const ksc_options o{dtype, space, KSC_DS_STENCIL, 0};
+  return ksc_create_opts(descs, n_curves, &o, hip_stream, out);
+}
+
+ksc_status ksc_create_opts(const ksc_curve_desc* descs, int32_t n_curves, const ksc_options* opts,
+                           void* hip_stream, ksc_problem** out) {
   g_err.clear();
-  if (!descs || !out) return fail(KSC_ERR_ARG, "ksc_create: null pointer");
+  if (!descs || !out || !opts) return fail(KSC_ERR_ARG, "ksc_create: null pointer");
   *out = nullptr;
+  const int dtype = opts->dtype, space = opts->space, ds = opts->ds;
   if (n_curves < 1) return fail(KSC_ERR_SHAPE, "ksc_create: n_curves must be >= 1");
   if (dtype != KSC_F32 && dtype != KSC_F64) return fail(KSC_ERR_ARG, "ksc_create: bad dtype");
   if (space != KSC_SPACE_FULL && space != KSC_SPACE_ODD)
     return fail(KSC_ERR_ARG, "ksc_create: bad state space");
+  if (ds != KSC_DS_STENCIL && ds != KSC_DS_SPECTRAL)
+    return fail(KSC_ERR_ARG, "ksc_create: bad d/ds option");
+  if (opts->reserved != 0) return fail(KSC_ERR_ARG, "ksc_create: reserved option must be 0");
+  if (ds == KSC_DS_SPECTRAL && space != KSC_SPACE_FULL)
+    return fail(KSC_ERR_UNSUPPORTED, "ksc_create: the spectral d/ds is built for the full space");
   for (int c = 0; c < n_curves; ++c) {
     const ksc_curve_desc& d = descs[c];
     if (!nx_supported(d.n_x))
@@ -700,6 +939,18 @@ ksc_status ksc_create2(const ksc_curve_desc* descs, int32_t n_curves, int32_t dt
       return fail(KSC_ERR_UNSUPPORTED, "ksc_create: curve " + std::to_string(c) +
                                            ": the inversion-symmetric subspace in FP64 "
                                            "supports n_x <= 128");
+    if (ds == KSC_DS_SPECTRAL) {
+      if (d.map != KSC_MAP_RATIONAL)
+        return fail(KSC_ERR_ARG, "ksc_create: curve " + std::to_string(c) +
+                                     ": the spectral d/ds needs the rational map");
+      if (d.n_x * (dtype == KSC_F64 ? 8 : 4) > 512)
+        return fail(KSC_ERR_UNSUPPORTED, "ksc_create: curve " + std::to_string(c) +
+                                             ": the spectral d/ds supports n_x <= " +
+                                             (dtype == KSC_F64 ? "64 in FP64" : "128 in FP32"));
+      if (d.n_s > 16384)
+        return fail(KSC_ERR_UNSUPPORTED, "ksc_create: curve " + std::to_string(c) +
+                                             ": the spectral d/ds supports n_s <= 16384");
+    }
     if (d.n_s < 3)
       return fail(KSC_ERR_SHAPE, "ksc_create: curve " + std::to_string(c) + ": n_s < 3");
     if (d.n_s > (1 << 26))
@@ -716,6 +967,7 @@ ksc_status ksc_create2(const ksc_curve_desc* descs, int32_t n_curves, int32_t dt
   p->nc = n_curves;
   p->dtype = dtype;
   p->space = space;
+  p->ds = ds;
   p->stream = static_cast<hipStream_t>(hip_stream);
   p->desc.assign(descs, descs + n_curves);
   auto cleanup = [&](ksc_status st) {
@@ -769,7 +1021,7 @@ ksc_status ksc_create2(const ksc_curve_desc* descs, int32_t n_curves, int32_t dt
     p->min_nx = std::min(p->min_nx, d.n_x);
     if (d.n_x != 32 && d.n_x != 64 && d.n_x != 128) p->mixed_ok = false;
   }
-  if (p->odd()) p->mixed_ok = false;  // one launch per distinct n_x
+  if (p->odd() || p->spectral()) p->mixed_ok = false;  // one launch per distinct n_x
   p->uniform = (p->max_nx == p->min_nx);
   p->rows_total = int(cs.size());
   p->modes_total = int(A.size());
@@ -820,6 +1072,7 @@ ksc_status ksc_create2(const ksc_curve_desc* descs, int32_t n_curves, int32_t dt
   if (p->W == 0)
     return cleanup(fail(KSC_ERR_UNSUPPORTED, "ksc_create: tile staging buffer exceeds LDS"));
   if ((st = build_tiles(p)) != KSC_OK) return cleanup(st);
+  if (p->spectral() && (st = setup_spectral(p)) != KSC_OK) return cleanup(st);
   if (hipStreamCreateWithFlags(&p->cap_stream, hipStreamNonBlocking) != hipSuccess)
     return cleanup(fail(KSC_ERR_HIP, "ksc_create: stream creation failed"));
   *out = p;
@@ -833,7 +1086,8 @@ ksc_status ksc_destroy(ksc_problem* p) {
   for (hipEvent_t e : p->tev) hipEventDestroy(e);
   void* bufs[] = {p->d_bounds, p->d_cd,  p->d_tiles, p->d_cs,    p->d_wlT,    p->d_wlD,
                   p->d_A,   p->d_pre,   p->d_sqrtL, p->d_part,   p->d_prevJ2,
-                  p->d_flags, p->d_J2,  p->d_edge};
+                  p->d_flags, p->d_J2,  p->d_edge,  p->d_dpool,  p->d_spec,  p->d_Y,
+                  p->d_WR,  p->d_P};
   for (void* b : bufs)
     if (b) hipFree(b);
   delete p;
@@ -1089,6 +1343,7 @@ ksc_status ksc_tune(ksc_problem* p, const char* cache_path) {
   std::ostringstream key;
   key << prop.gcnArchName << "|" << rt << "|" << (p->dtype == KSC_F64 ? "f64" : "f32") << "|";
   if (p->odd()) key << "odd|";
+  if (p->spectral()) key << "spec|";
   for (const auto& d : p->desc) key << d.n_x << "x" << d.n_s << ";";
   std::string kstr = key.str();
   // a long key is hashed to keep the file small

@@ -1,0 +1,342 @@
+// Evaluation with the paper's spectral d/ds: the rational Chebyshev
+// differentiation matrix D_t (Sec. IV, eq. rational_diff_matrix) applied along
+// s, instead of the central difference of the tile kernels.
+//
+// D_t is dense, so one evaluation is three launches (plus the cost reduction):
+//   1. Y = D_t U per curve, a matrix product along s (MFMA, spec_gemm);
+//   2. per row (spec_row_body): r_hat = -Y + A u_hat - (i q / 2) N_hat, the
+//      cost partials, and the row-local part of the adjoint
+//      P = Q_hat + A r_hat (Q_hat: the u r_x term); the row writes
+//      WR = 2 w L r_hat and P;
+//   3. Z' = D_t^T WR per curve (MFMA), whose epilogue forms the output:
+//      L^dagger r = P - Z' / (2 w L) (the s-part -(1/w) D_t^T (w r) is the
+//      exact discrete adjoint of -D_t in the weighted inner product), and the
+//      gradient 2 w L c_k L^dagger r = c_k (2 w L P - Z') or the step
+//      u_hat - dtau L^dagger r / (1 + dtau A^2).
+// The matrix pool holds D~ = S D_t per distinct N_s (it does not depend on S)
+// in FP64; 1/S is applied in the epilogues.  The products run on FP64 matrix
+// cores for both state dtypes: the sums along s cancel heavily (at N_s = 552
+// the sum of the magnitudes of the terms of the adjoint's s-part is ~3e3 times
+// the result), so FP32 storage of D~ or FP32 accumulation would lose about
+// three digits, while FP32 rounding of the state and of the residual alone
+// stays near 1e-6 of the gradient.
+#pragma once
+
+#include "ksc_tile.hpp"
+
+namespace ksc {
+
+// Per-curve descriptor of the spectral launches.
+struct SpecDev {
+  long long off;   // offset of row 0 in complex elements of the state
+  long long dmat;  // offset of the curve's D~ (n_s x n_s, row-major) in the matrix pool
+  int n_s, km, row_off, mode_off;
+  int c, pad_;     // index of the curve in the problem
+  double inv_S;    // 1 / S
+};
+
+template <typename T>
+struct SpecArgs {
+  const double* __restrict__ dpool;     // D~ matrices (FP64)
+  const SpecDev* __restrict__ curves;
+  const T* __restrict__ b;              // GEMM right operand (state layout)
+  T* __restrict__ out;                  // GEMM result or final output (state layout)
+  const T* __restrict__ u;              // state (STEP epilogue)
+  const T* __restrict__ p;              // row-local adjoint part P (GRAD/STEP epilogue)
+  const T* __restrict__ wlT;            // per row: 2 w L
+  const T* __restrict__ pre;            // per mode: -dtau / (1 + dtau A^2)
+  const double* __restrict__ scale;     // per curve gradient scale, nullable
+  const unsigned char* __restrict__ active;  // per curve, nullable (STEP)
+};
+
+enum SpecEpi : int { EPI_Y = 0, EPI_GRAD = 1, EPI_STEP = 2 };
+
+// Row kernel arguments: the tile machinery's KernelArgs (state in a.in, tiles,
+// tables, partials) plus the derivative rows Y and the two output arrays.
+template <typename T>
+struct SpecRowArgs {
+  KernelArgs<T> a;
+  const cplx<T>* __restrict__ y;  // D_t U
+  cplx<T>* __restrict__ wr;       // 2 w L r_hat (0 on the end rows)
+  cplx<T>* __restrict__ pl;       // Q_hat + A r_hat (0 on the end rows)
+};
+
+// One tile of 64W rows, one row per lane (N_x sizeof(T) <= 512 B): the
+// residual from the precomputed d/ds rows, the cost and J_arc partials and,
+// unless MODE_J, the row-local adjoint part.
+template <int NX, typename T, int W, int MODE>
+__device__ __forceinline__ void spec_row_body(const SpecRowArgs<T>& sa, const CurveDev& cd, int c,
+                                              int j0, int tile, cplx<T>* buf) {
+  const KernelArgs<T>& a = sa.a;
+  constexpr int KM = (NX - 1) / 3 + 1;
+  constexpr int ROWS = 64 * W;
+  constexpr int E = 16 / int(sizeof(cplx<T>));
+  constexpr int NB = ROWS * KM + 2 * E;  // one staged block, with alignment slack
+  const int t = threadIdx.x;
+  const int n_s = cd.n_s;
+  const int jr = j0 + t;
+  const bool interior = (jr >= 1) && (jr <= n_s - 2);
+  const long long base = cd.off + (long long)j0 * KM;
+  const long long G_hi = cd.off + (long long)min(n_s, j0 + ROWS) * KM;
+  const int sh = int(base % E);
+  cplx<T>* __restrict__ bu = buf;       // state rows
+  cplx<T>* __restrict__ by = buf + NB;  // d/ds rows
+  __syncthreads();
+  stage_block<cplx<T>, ROWS, ROWS * KM + E>(bu, a.in, base, sh, ROWS * KM + sh, base, G_hi);
+  stage_block<cplx<T>, ROWS, ROWS * KM + E>(by, sa.y, base, sh, ROWS * KM + sh, base, G_hi);
+  __syncthreads();
+  const cplx<T>* __restrict__ urow = bu + sh + t * KM;
+  const cplx<T>* __restrict__ yrow = by + sh + t * KM;
+
+  const T q1s = T(cd.q1 * cd.q1);
+  const T qN1 = T(cd.q1 / (4.0 * NX));  // q1 / (4 N_x): S is 2 N_x N_hat
+  const T qY1 = T(cd.q1 / (2.0 * NX));  // q1 / (2 N_x): Q_hat = r2c/(2 N_x)
+
+  cplx<T> In[KM];
+  sfor<KM>([&](auto Kk) {
+    constexpr int k = Kk;
+    cplx<T> v = urow[k];
+    if (k == 0) v.i = T(0);
+    In[k] = v;
+  });
+  T u[NX];
+  cplx<T> S[KM];
+  {
+    T v[NX];
+    spec_to_phys<NX, KM, T>(In, v);
+    sfor<NX>([&](auto Nn) {
+      constexpr int n = Nn;
+      if constexpr (MODE != MODE_J) u[n] = v[n];
+      v[n] = v[n] * v[n];
+    });
+    phys_to_spec2<NX, KM, T>(v, S);
+  }
+  // r_hat = -D_t u_hat + A u_hat - (i q / 2) N_hat,  S = 2 N_x N_hat
+  cplx<T> R[KM];
+  T rowR0 = T(0), rowR = T(0), rowD0 = T(0), rowD = T(0);
+  sfor<KM>([&](auto Kk) {
+    constexpr int k = Kk;
+    const cplx<T> yk = yrow[k];
+    T rr, ri;
+    if constexpr (k == 0) {
+      rr = -yk.r;
+      ri = T(0);
+      rowR0 = rr * rr;
+      rowD0 = yk.r * yk.r;
+    } else {
+      const T qn = T(k) * qN1;
+      const T q2 = T(k * k) * q1s;
+      const T Ak = fmaT(-q2, q2, q2);
+      rr = fmaT(Ak, In[k].r, fmaT(qn, S[k].i, -yk.r));
+      ri = fmaT(Ak, In[k].i, fmaT(-qn, S[k].r, -yk.i));
+      rowR = fmaT(rr, rr, fmaT(ri, ri, rowR));
+      rowD = fmaT(yk.r, yk.r, fmaT(yk.i, yk.i, rowD));
+    }
+    R[k] = interior ? cplx<T>{rr, ri} : cplx<T>{T(0), T(0)};
+  });
+  double pj = 0.0, pn = 0.0, pd = 0.0;
+  if (interior) {
+    const double rR = double(rowR0) + 2.0 * double(rowR);
+    const double wl = a.wlD[cd.row_off + jr];  // w_j L
+    pj = wl * rR;
+    if constexpr (MODE == MODE_J) {
+      // J_arc: |u_s| ds = |D_t u|_j w_j (the common factor L cancels)
+      const double rD = double(rowD0) + 2.0 * double(rowD);
+      pn = wl * sqrt(rR * rD);
+      pd = wl * sqrt(rD);
+    }
+  }
+  store_wave_partials<W, (MODE == MODE_J) ? 3 : 1>(pj, pn, pd, tile_partials(a, cd, c, tile, W));
+  if constexpr (MODE != MODE_J) {
+    // Q_hat = r2c(u * c2r((i q / (2 N_x)) r_hat))
+    sfor<KM>([&](auto Kk) {
+      constexpr int k = Kk;
+      const T qk = T(k) * qY1;
+      In[k] = cplx<T>{-qk * R[k].i, qk * R[k].r};
+    });
+    {
+      T v[NX];
+      spec_to_phys<NX, KM, T>(In, v);
+      sfor<NX>([&](auto Nn) {
+        constexpr int n = Nn;
+        v[n] = u[n] * v[n];
+      });
+      phys_to_spec2<NX, KM, T>(v, S);
+    }
+    const T f0 = interior ? a.wlT[cd.row_off + jr] : T(0);  // 2 w L
+    // outputs through the staging buffers (coalesced writes)
+    __syncthreads();
+    cplx<T>* __restrict__ ow = bu + sh + t * KM;
+    cplx<T>* __restrict__ op = by + sh + t * KM;
+    sfor<KM>([&](auto Kk) {
+      constexpr int k = Kk;
+      const T q2 = T(k * k) * q1s;
+      const T Ak = fmaT(-q2, q2, q2);
+      ow[k] = cplx<T>{f0 * R[k].r, f0 * R[k].i};
+      const T pr = fmaT(Ak, R[k].r, S[k].r);
+      const T pi = (k == 0) ? T(0) : fmaT(Ak, R[k].i, S[k].i);
+      op[k] = interior ? cplx<T>{pr, pi} : cplx<T>{T(0), T(0)};
+    });
+    __syncthreads();
+    flush_block<cplx<T>, ROWS, ROWS * KM + E, false>(sa.wr, nullptr, bu, base, sh, ROWS * KM + sh,
+                                                     base, G_hi);
+    flush_block<cplx<T>, ROWS, ROWS * KM + E, false>(sa.pl, nullptr, by, base, sh, ROWS * KM + sh,
+                                                     base, G_hi);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// C = op(D~) B / S per curve on FP64 matrix cores: D~ is n_s x n_s (op = transpose
+// for TRANS), B the curve's state viewed as an n_s x NC real matrix (NC =
+// 2(K+1), row stride NC).  A workgroup of four waves computes 64 rows x NCP
+// columns (NCP = NC rounded up to 16); wave w owns rows 16w .. 16w+15 and all
+// column tiles; the k loop walks n_s in steps of 16, the next step's operands
+// loaded into registers while the current step's products run.
+//
+// 16x16x4 MFMA lane layout: lane l supplies A[l % 16][l / 16] and
+// B[l / 16][l % 16]; accumulator r of lane l holds C[i][l % 16] with
+// i = 4 (l / 16) + r for FP32 and i = l / 16 + 4 r for FP64 (checked on the
+// device against a host product).
+// ---------------------------------------------------------------------------
+template <typename T>
+struct mfma_acc;
+template <>
+struct mfma_acc<float> {
+  typedef float v __attribute__((ext_vector_type(4)));
+  __device__ __forceinline__ static v mac(float a, float b, v c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+  __device__ __forceinline__ static int row(int lane, int r) { return 4 * (lane >> 4) + r; }
+};
+template <>
+struct mfma_acc<double> {
+  typedef double v __attribute__((ext_vector_type(4)));
+  __device__ __forceinline__ static v mac(double a, double b, v c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+  __device__ __forceinline__ static int row(int lane, int r) { return (lane >> 4) + 4 * r; }
+};
+
+template <typename T, int NCP, bool TRANS, int EPI>
+__device__ __forceinline__ void spec_gemm_body(const SpecArgs<T>& sa, const SpecDev& cd, int row0,
+                                               double* lds) {
+  const int c = cd.c;
+  using mma = mfma_acc<double>;
+  using acc_t = typename mma::v;
+  constexpr int BM = 64, BK = 16;
+  constexpr int NT = NCP / 16;               // column tiles per wave
+  constexpr int BE = (BK * NCP) / 256;       // B elements per thread and k step
+  static_assert((BK * NCP) % 256 == 0, "B tile must split evenly over 256 threads");
+  const int t = threadIdx.x;
+  const int lane = t & 63, w = t >> 6;
+  const int n_s = cd.n_s;
+  const int NC = 2 * cd.km;
+  const double* __restrict__ D = sa.dpool + cd.dmat;
+  const T* __restrict__ B = sa.b + 2 * cd.off;
+  double* As = lds;               // [BK][BM]
+  double* Bs = lds + BK * BM;     // [BK][NCP]
+
+  double ra[4], rb[BE];
+  auto load = [&](int k0) {
+    // A tile: op(D~)[row0 + i][k0 + kk], i < 64, kk < 16, four per thread
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      int i, kk;
+      if constexpr (TRANS) {  // D~[k][i]: 64 consecutive i for each k
+        kk = (t >> 4);
+        i = ((t & 15) << 2) + e;
+      } else {                // D~[i][k]: 16 consecutive k for each i
+        i = t >> 2;
+        kk = ((t & 3) << 2) + e;
+      }
+      const int gi = row0 + i, gk = k0 + kk;
+      double v = 0.0;
+      if (gi < n_s && gk < n_s) v = TRANS ? D[(long long)gk * n_s + gi] : D[(long long)gi * n_s + gk];
+      ra[e] = v;
+    }
+#pragma unroll
+    for (int e = 0; e < BE; ++e) {
+      const int q = t + 256 * e;
+      const int kk = q / NCP, col = q % NCP;
+      const int gk = k0 + kk;
+      rb[e] = (gk < n_s && col < NC) ? double(B[(long long)gk * NC + col]) : 0.0;
+    }
+  };
+  auto store = [&]() {
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      int i, kk;
+      if constexpr (TRANS) {
+        kk = (t >> 4);
+        i = ((t & 15) << 2) + e;
+      } else {
+        i = t >> 2;
+        kk = ((t & 3) << 2) + e;
+      }
+      As[kk * BM + i] = ra[e];
+    }
+#pragma unroll
+    for (int e = 0; e < BE; ++e) Bs[t + 256 * e] = rb[e];  // [kk][col] with q = kk*NCP + col
+  };
+
+  acc_t acc[NT];
+#pragma unroll
+  for (int j = 0; j < NT; ++j) acc[j] = acc_t{0.0, 0.0, 0.0, 0.0};
+  load(0);
+  for (int k0 = 0; k0 < n_s; k0 += BK) {
+    __syncthreads();  // the previous step's reads of the tiles are done
+    store();
+    __syncthreads();
+    if (k0 + BK < n_s) load(k0 + BK);
+#pragma unroll
+    for (int s = 0; s < BK / 4; ++s) {
+      const int kk = 4 * s + (lane >> 4);
+      const double av = As[kk * BM + 16 * w + (lane & 15)];
+#pragma unroll
+      for (int j = 0; j < NT; ++j) {
+        const double bv = Bs[kk * NCP + 16 * j + (lane & 15)];
+        acc[j] = mma::mac(av, bv, acc[j]);
+      }
+    }
+  }
+
+  // epilogue: element (row, col) of C, col = 2k + (0: re, 1: im); the
+  // product is rounded to the state dtype, the rest as in the row kernels
+  const double inv_S = cd.inv_S;
+  const bool act = (sa.active == nullptr) || sa.active[c] != 0;
+  const T sc = (EPI == EPI_GRAD && sa.scale != nullptr) ? T(sa.scale[c]) : T(1);
+  T* __restrict__ O = sa.out + 2 * cd.off;
+#pragma unroll
+  for (int j = 0; j < NT; ++j) {
+    const int col = 16 * j + (lane & 15);
+    const int k = col >> 1;
+    const bool im0 = (col == 1);
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int row = row0 + 16 * w + mma::row(lane, r);
+      if (row >= n_s || col >= NC) continue;
+      const long long idx = (long long)row * NC + col;
+      const T z = T(acc[j][r] * inv_S);
+      const bool interior = row >= 1 && row <= n_s - 2;
+      if constexpr (EPI == EPI_Y) {
+        O[idx] = z;
+      } else if constexpr (EPI == EPI_GRAD) {
+        const T pv = sa.p[2 * cd.off + idx];
+        const T f = sa.wlT[cd.row_off + row];
+        const T ck = (k == 0) ? T(1) : T(2);
+        O[idx] = (interior && !im0) ? (ck * sc) * fmaT(f, pv, -z) : T(0);
+      } else {
+        const T uv = sa.u[2 * cd.off + idx];
+        T o = uv;
+        if (interior && act) {
+          const T pv = sa.p[2 * cd.off + idx];
+          const T f = sa.wlT[cd.row_off + row];
+          o = fmaT(sa.pre[cd.mode_off + k], pv - z / f, uv);
+        }
+        O[idx] = im0 ? T(0) : o;
+      }
+    }
+  }
+}
+
+}  // namespace ksc

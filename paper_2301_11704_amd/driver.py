@@ -81,7 +81,7 @@ class GpuBackend:
         """The same curves continued in FP64."""
         from .problem import Problem
         p64 = Problem(self.prob.curves, dtype=self._torch.float64, device=self.state.device,
-                      space=self.prob.space)
+                      space=self.prob.space, ds=self.prob.ds)
         b = GpuBackend(p64, self.state.double())
         b.active.copy_(self.active)
         return b

@@ -56,24 +56,30 @@ class Problem:
     c as [n_s, K+1, 2].
     space="odd" (inversion-symmetric subspace, u_hat_k = i b_k): rows of the K
     reals b_1..b_K; ``view(state, c)`` gives [n_s, K].
+    ds="spectral": d/ds is the paper's rational Chebyshev D_t (rational map).
     """
 
-    def __init__(self, curves, dtype=torch.float32, device="cuda", space="full"):
+    def __init__(self, curves, dtype=torch.float32, device="cuda", space="full", ds="stencil"):
         self.curves = [c if isinstance(c, CurveDesc) else CurveDesc(**c) for c in curves]
         if dtype not in (torch.float32, torch.float64):
             raise ValueError("dtype must be torch.float32 or torch.float64")
         spaces = {"full": _lib.KSC_SPACE_FULL, "odd": _lib.KSC_SPACE_ODD}
         if space not in spaces:
             raise ValueError("space must be 'full' or 'odd'")
+        dss = {"stencil": _lib.KSC_DS_STENCIL, "spectral": _lib.KSC_DS_SPECTRAL}
+        if ds not in dss:
+            raise ValueError("ds must be 'stencil' or 'spectral'")
         self.space = space
+        self.ds = ds
         self.dtype = dtype
         self.device = torch.device(device)
         arr = (_lib.CurveDescC * len(self.curves))(*[c.to_c() for c in self.curves])
         h = ctypes.c_void_p()
         dt = _lib.KSC_F64 if dtype == torch.float64 else _lib.KSC_F32
+        opts = _lib.OptionsC(dt, spaces[space], dss[ds], 0)
         with torch.cuda.device(self.device):
-            check(lib().ksc_create2(arr, len(self.curves), dt, spaces[space], self._stream(),
-                                    ctypes.byref(h)))
+            check(lib().ksc_create_opts(arr, len(self.curves), ctypes.byref(opts), self._stream(),
+                                        ctypes.byref(h)))
         self._h = h
         L = lib()
         self.numel = int(L.ksc_state_numel(h))

@@ -99,3 +99,30 @@ def test_create2_validates_the_state_space():
     assert b"n_x <= 128" in L.ksc_last_error()
     assert create2(_lib.KSC_SPACE_ODD, _lib.KSC_F64, 48) == -3
     assert out.value is None
+
+
+def test_create_opts_validates_the_spectral_ds():
+    """ksc_create_opts: the spectral d/ds needs the rational map, the full
+    space, one row per lane (n_x <= 128 in FP32, <= 64 in FP64) and
+    n_s <= 16384; unknown options and a non-zero reserved field are argument
+    errors; all reported before any HIP call."""
+    from paper_2301_11704_amd import _lib
+    if not os.path.exists(_lib.LIB_PATH):
+        pytest.skip("libksc.so not built")
+    L = _lib.lib()
+    out = ctypes.c_void_p()
+
+    def create(dtype=0, space=0, ds=1, reserved=0, n_x=32, n_s=64, map_=0):
+        arr = (_lib.CurveDescC * 1)(_lib.CurveDescC(n_s, n_x, 22.0, map_, 40.0, 0.0))
+        o = _lib.OptionsC(dtype, space, ds, reserved)
+        return L.ksc_create_opts(arr, 1, ctypes.byref(o), None, ctypes.byref(out))
+
+    assert L.ksc_create_opts(None, 1, None, None, ctypes.byref(out)) == -1
+    assert create(ds=2) == -1
+    assert create(reserved=1) == -1
+    assert create(map_=1) == -1 and b"rational" in L.ksc_last_error()
+    assert create(space=1) == -3
+    assert create(n_x=256) == -3
+    assert create(dtype=1, n_x=128) == -3 and b"64 in FP64" in L.ksc_last_error()
+    assert create(n_s=16385) == -3
+    assert out.value is None
