@@ -260,12 +260,13 @@ struct ksc_problem {
   int part_cap = 0;
   double pre_dtau = std::nan("");
 
-  // spectral d/ds: D~ = S D_t per distinct n_s, per-curve descriptors in tile
-  // order, one group of curves per n_x, and three state-sized work arrays
+  // spectral d/ds: D~ = S D_t per distinct n_s, per-curve descriptors ordered
+  // by (n_x, n_s), one group of curves per (n_x, n_s), and three state-sized
+  // work arrays
   void* d_dpool = nullptr;
   SpecDev* d_spec = nullptr;
   struct SpecGroup {
-    int nx, first, count, max_ns;
+    int nx, first, count, n_s;
   };
   std::vector<SpecGroup> spec_groups;
   void* d_Y = nullptr;
@@ -617,24 +618,24 @@ ksc_status launch_post(ksc_problem* p, int mode, const void* in, void* out, cons
 
 // ------------------------------------------------------- spectral d/ds --
 
-hipError_t spec_gemm(int nx, int epi, dim3 grid, hipStream_t s, const ksc::SpecArgs<float>& a,
-                     hipEvent_t e0, hipEvent_t e1) {
+hipError_t spec_gemm(int nx, int epi, int n_s, int count, hipStream_t s,
+                     const ksc::SpecArgs<float>& a, hipEvent_t e0, hipEvent_t e1) {
   switch (nx) {
-    case 8: return ksc::launch_spec_gemm_f32_8(epi, grid, s, a, e0, e1);
-    case 16: return ksc::launch_spec_gemm_f32_16(epi, grid, s, a, e0, e1);
-    case 32: return ksc::launch_spec_gemm_f32_32(epi, grid, s, a, e0, e1);
-    case 64: return ksc::launch_spec_gemm_f32_64(epi, grid, s, a, e0, e1);
-    case 128: return ksc::launch_spec_gemm_f32_128(epi, grid, s, a, e0, e1);
+    case 8: return ksc::launch_spec_gemm_f32_8(epi, n_s, count, s, a, e0, e1);
+    case 16: return ksc::launch_spec_gemm_f32_16(epi, n_s, count, s, a, e0, e1);
+    case 32: return ksc::launch_spec_gemm_f32_32(epi, n_s, count, s, a, e0, e1);
+    case 64: return ksc::launch_spec_gemm_f32_64(epi, n_s, count, s, a, e0, e1);
+    case 128: return ksc::launch_spec_gemm_f32_128(epi, n_s, count, s, a, e0, e1);
     default: return hipErrorInvalidValue;
   }
 }
-hipError_t spec_gemm(int nx, int epi, dim3 grid, hipStream_t s, const ksc::SpecArgs<double>& a,
-                     hipEvent_t e0, hipEvent_t e1) {
+hipError_t spec_gemm(int nx, int epi, int n_s, int count, hipStream_t s,
+                     const ksc::SpecArgs<double>& a, hipEvent_t e0, hipEvent_t e1) {
   switch (nx) {
-    case 8: return ksc::launch_spec_gemm_f64_8(epi, grid, s, a, e0, e1);
-    case 16: return ksc::launch_spec_gemm_f64_16(epi, grid, s, a, e0, e1);
-    case 32: return ksc::launch_spec_gemm_f64_32(epi, grid, s, a, e0, e1);
-    case 64: return ksc::launch_spec_gemm_f64_64(epi, grid, s, a, e0, e1);
+    case 8: return ksc::launch_spec_gemm_f64_8(epi, n_s, count, s, a, e0, e1);
+    case 16: return ksc::launch_spec_gemm_f64_16(epi, n_s, count, s, a, e0, e1);
+    case 32: return ksc::launch_spec_gemm_f64_32(epi, n_s, count, s, a, e0, e1);
+    case 64: return ksc::launch_spec_gemm_f64_64(epi, n_s, count, s, a, e0, e1);
     default: return hipErrorInvalidValue;
   }
 }
@@ -676,9 +677,6 @@ ksc_status launch_spectral(ksc_problem* p, int mode, const void* in, void* out,
   ga.pre = static_cast<const T*>(p->d_pre);
   ga.scale = scale;
   ga.active = active;
-  auto grid_of = [](const ksc_problem::SpecGroup& g) {
-    return dim3((g.max_ns + ksc::kSpecRowsPerBlock - 1) / ksc::kSpecRowsPerBlock, g.count);
-  };
   // 1. Y = D_t U
   for (int g = 0; g < ng; ++g) {
     const auto& G = p->spec_groups[g];
@@ -686,7 +684,8 @@ ksc_status launch_spectral(ksc_problem* p, int mode, const void* in, void* out,
     a.curves = p->d_spec + G.first;
     a.b = static_cast<const T*>(in);
     a.out = static_cast<T*>(p->d_Y);
-    hipError_t e = spec_gemm(G.nx, ksc::EPI_Y, grid_of(G), s, a, g == 0 ? e_first : nullptr, nullptr);
+    hipError_t e = spec_gemm(G.nx, ksc::EPI_Y, G.n_s, G.count, s, a, g == 0 ? e_first : nullptr,
+                             nullptr);
     if (e != hipSuccess) return fail(KSC_ERR_HIP, std::string("spectral product: ") + hipGetErrorString(e));
   }
   // 2. rows: residual, cost partials, row-local adjoint part
@@ -722,8 +721,8 @@ ksc_status launch_spectral(ksc_problem* p, int mode, const void* in, void* out,
     a.p = static_cast<const T*>(p->d_P);
     a.u = static_cast<const T*>(in);
     a.out = static_cast<T*>(out);
-    hipError_t e = spec_gemm(G.nx, mode == ksc::MODE_GRAD ? ksc::EPI_GRAD : ksc::EPI_STEP,
-                             grid_of(G), s, a, nullptr, g == ng - 1 ? e_last : nullptr);
+    hipError_t e = spec_gemm(G.nx, mode == ksc::MODE_GRAD ? ksc::EPI_GRAD : ksc::EPI_STEP, G.n_s,
+                             G.count, s, a, nullptr, g == ng - 1 ? e_last : nullptr);
     if (e != hipSuccess) return fail(KSC_ERR_HIP, std::string("spectral product: ") + hipGetErrorString(e));
   }
   return KSC_OK;
@@ -782,7 +781,12 @@ ksc_status setup_spectral(ksc_problem* p) {
   }
   std::vector<SpecDev> sd;
   p->spec_groups.clear();
-  for (int c : p->curve_order) {
+  std::vector<int> order(p->curve_order);
+  std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
+    const CurveDev &x = p->cd[a], &y = p->cd[b];
+    return x.n_x != y.n_x ? x.n_x > y.n_x : x.n_s < y.n_s;
+  });
+  for (int c : order) {
     const CurveDev& d = p->cd[c];
     const size_t mi = std::lower_bound(sizes.begin(), sizes.end(), d.n_s) - sizes.begin();
     SpecDev s{};
@@ -794,11 +798,10 @@ ksc_status setup_spectral(ksc_problem* p) {
     s.mode_off = d.mode_off;
     s.c = c;
     s.inv_S = 1.0 / p->desc[c].scale;
-    if (p->spec_groups.empty() || p->spec_groups.back().nx != d.n_x)
-      p->spec_groups.push_back({d.n_x, int(sd.size()), 0, 0});
-    auto& G = p->spec_groups.back();
-    G.count++;
-    G.max_ns = std::max(G.max_ns, d.n_s);
+    if (p->spec_groups.empty() || p->spec_groups.back().nx != d.n_x ||
+        p->spec_groups.back().n_s != d.n_s)
+      p->spec_groups.push_back({d.n_x, int(sd.size()), 0, d.n_s});
+    p->spec_groups.back().count++;
     sd.push_back(s);
   }
   KSC_HIP(hipMalloc(&p->d_spec, sd.size() * sizeof(SpecDev)));

@@ -20,10 +20,10 @@ constexpr bool spec_supported() {
   return NX * int(sizeof(T)) <= 512;
 }
 
-// epi: EPI_Y (Y = D_t B), EPI_GRAD or EPI_STEP (with op(D~) = D~^T).  grid.x
-// covers the largest n_s of the group in blocks of 64 rows, grid.y its curves.
+// epi: EPI_Y (Y = D_t B), EPI_GRAD or EPI_STEP (with op(D~) = D~^T) over a
+// group of `count` curves (a.curves) that share n_x and n_s.
 #define KSC_DECLARE_SPEC(TNAME, T, NX)                                                          \
-  hipError_t launch_spec_gemm_##TNAME##_##NX(int epi, dim3 grid, hipStream_t s,                 \
+  hipError_t launch_spec_gemm_##TNAME##_##NX(int epi, int n_s, int count, hipStream_t s,        \
                                              const SpecArgs<T>& a, hipEvent_t e0, hipEvent_t e1); \
   hipError_t launch_spec_row_##TNAME##_##NX(int W, int mode, int grid, size_t lds, hipStream_t s, \
                                             const SpecRowArgs<T>& a, hipEvent_t e0, hipEvent_t e1);

@@ -12,13 +12,13 @@
 
 namespace ksc {
 
+// grid.x: row blocks of 64, grid.y: blocks of spec_cb<NCP>() curves of one
+// group (curves sharing n_x and n_s); `count` curves in the group.
 template <typename T, int NCP, bool TRANS, int EPI>
-__global__ __launch_bounds__(256) void spec_gemm_kernel(SpecArgs<T> sa) {
-  __shared__ __align__(16) double lds[16 * kSpecRowsPerBlock + 16 * NCP];
-  const SpecDev cd = sa.curves[blockIdx.y];
-  const int row0 = blockIdx.x * kSpecRowsPerBlock;
-  if (row0 >= cd.n_s) return;  // uniform over the workgroup
-  spec_gemm_body<T, NCP, TRANS, EPI>(sa, cd, row0, lds);
+__global__ __launch_bounds__(256) void spec_gemm_kernel(SpecArgs<T> sa, int count) {
+  __shared__ __align__(16) double lds[spec_gemm_lds<NCP>()];
+  spec_gemm_body<T, NCP, TRANS, EPI>(sa, count, int(blockIdx.y) * spec_cb<NCP>(),
+                                     int(blockIdx.x) * kSpecRowsPerBlock, lds);
 }
 
 template <int NX, typename T, int W, int MODE>
@@ -70,20 +70,23 @@ hipError_t KSC_CAT(KSC_CAT(KSC_CAT(launch_spec_row_, KSC_TNAME), _), KSC_NX)(
 }
 
 hipError_t KSC_CAT(KSC_CAT(KSC_CAT(launch_spec_gemm_, KSC_TNAME), _), KSC_NX)(
-    int epi, dim3 grid, hipStream_t s, const SpecArgs<KSC_T>& a, hipEvent_t e0, hipEvent_t e1) {
+    int epi, int n_s, int count, hipStream_t s, const SpecArgs<KSC_T>& a, hipEvent_t e0,
+    hipEvent_t e1) {
   constexpr int NCP = spec_ncp(KSC_NX);
+  constexpr int CB = spec_cb<NCP>();
+  const dim3 grid((n_s + kSpecRowsPerBlock - 1) / kSpecRowsPerBlock, (count + CB - 1) / CB);
   if constexpr (!spec_supported<KSC_NX, KSC_T>()) {
     return hipErrorInvalidValue;
   } else {
     switch (epi) {
       case EPI_Y:
-        hipExtLaunchKernelGGL((spec_gemm_kernel<KSC_T, NCP, false, EPI_Y>), grid, dim3(256), 0, s, e0, e1, 0, a);
+        hipExtLaunchKernelGGL((spec_gemm_kernel<KSC_T, NCP, false, EPI_Y>), grid, dim3(256), 0, s, e0, e1, 0, a, count);
         break;
       case EPI_GRAD:
-        hipExtLaunchKernelGGL((spec_gemm_kernel<KSC_T, NCP, true, EPI_GRAD>), grid, dim3(256), 0, s, e0, e1, 0, a);
+        hipExtLaunchKernelGGL((spec_gemm_kernel<KSC_T, NCP, true, EPI_GRAD>), grid, dim3(256), 0, s, e0, e1, 0, a, count);
         break;
       default:
-        hipExtLaunchKernelGGL((spec_gemm_kernel<KSC_T, NCP, true, EPI_STEP>), grid, dim3(256), 0, s, e0, e1, 0, a);
+        hipExtLaunchKernelGGL((spec_gemm_kernel<KSC_T, NCP, true, EPI_STEP>), grid, dim3(256), 0, s, e0, e1, 0, a, count);
         break;
     }
     return hipGetLastError();

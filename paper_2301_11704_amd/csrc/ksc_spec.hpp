@@ -188,10 +188,12 @@ __device__ __forceinline__ void spec_row_body(const SpecRowArgs<T>& sa, const Cu
 // ---------------------------------------------------------------------------
 // C = op(D~) B / S per curve on FP64 matrix cores: D~ is n_s x n_s (op = transpose
 // for TRANS), B the curve's state viewed as an n_s x NC real matrix (NC =
-// 2(K+1), row stride NC).  A workgroup of four waves computes 64 rows x NCP
-// columns (NCP = NC rounded up to 16); wave w owns rows 16w .. 16w+15 and all
-// column tiles; the k loop walks n_s in steps of 16, the next step's operands
-// loaded into registers while the current step's products run.
+// 2(K+1), row stride NC).  A workgroup of four waves computes 64 rows of CB
+// curves that share n_s (NCP = NC rounded up to 16 columns each, CB chosen for
+// about six column tiles per wave, so one A tile feeds six accumulators); wave
+// w owns rows 16w .. 16w+15 and all column tiles; the k loop walks n_s in
+// steps of 32, the next step's operands loaded into registers while the
+// current step's products run.
 //
 // 16x16x4 MFMA lane layout: lane l supplies A[l % 16][l / 16] and
 // B[l / 16][l % 16]; accumulator r of lane l holds C[i][l % 16] with
@@ -217,71 +219,106 @@ struct mfma_acc<double> {
   __device__ __forceinline__ static int row(int lane, int r) { return (lane >> 4) + 4 * r; }
 };
 
+// Curves per workgroup of the products: one where a curve already gives a
+// wave three or more 16-column tiles (a larger block would leave too few
+// workgroups to fill the chip for batches of a few hundred rows per curve),
+// else enough curves for about three tiles.
+template <int NCP>
+constexpr int spec_cb() {
+  return (NCP / 16) >= 3 ? 1 : (NCP / 16) == 2 ? 2 : 3;
+}
+// LDS of one product workgroup (doubles): the A and B tiles with padded rows.
+template <int NCP>
+constexpr int spec_gemm_lds() {
+  constexpr int BW = spec_cb<NCP>() * NCP;
+  return 32 * (64 + 16) + 32 * (BW + ((48 - BW % 32) % 32));
+}
+
+// Rows row0 .. row0+63 of C for the curves cbase .. cbase+CB-1 of a group of
+// `count` curves that share n_s (and hence D~).
 template <typename T, int NCP, bool TRANS, int EPI>
-__device__ __forceinline__ void spec_gemm_body(const SpecArgs<T>& sa, const SpecDev& cd, int row0,
-                                               double* lds) {
-  const int c = cd.c;
+__device__ __forceinline__ void spec_gemm_body(const SpecArgs<T>& sa, int count, int cbase,
+                                               int row0, double* lds) {
   using mma = mfma_acc<double>;
   using acc_t = typename mma::v;
-  constexpr int BM = 64, BK = 16;
-  constexpr int NT = NCP / 16;               // column tiles per wave
-  constexpr int BE = (BK * NCP) / 256;       // B elements per thread and k step
-  static_assert((BK * NCP) % 256 == 0, "B tile must split evenly over 256 threads");
+  constexpr int BM = 64, BK = 32;
+  constexpr int AE = BM * BK / 256;          // A elements per thread and k step
+  constexpr int CB = spec_cb<NCP>();
+  constexpr int NT = NCP / 16;               // column tiles per curve
+  constexpr int NJ = CB * NT;                // column tiles per wave
+  constexpr int BW = CB * NCP;               // B tile width
+  // LDS row strides: the four 16-lane groups of an MFMA operand read hit
+  // alternating halves of the 64 banks (stride = 16 mod 32 doubles)
+  constexpr int SA = BM + 16;
+  constexpr int SB = BW + ((48 - BW % 32) % 32);
+  constexpr int BE = (BK * BW) / 256;        // B elements per thread and k step
+  static_assert((BK * BW) % 256 == 0, "B tile must split evenly over 256 threads");
   const int t = threadIdx.x;
   const int lane = t & 63, w = t >> 6;
-  const int n_s = cd.n_s;
-  const int NC = 2 * cd.km;
-  const double* __restrict__ D = sa.dpool + cd.dmat;
-  const T* __restrict__ B = sa.b + 2 * cd.off;
-  double* As = lds;               // [BK][BM]
-  double* Bs = lds + BK * BM;     // [BK][NCP]
-
-  double ra[4], rb[BE];
-  auto load = [&](int k0) {
-    // A tile: op(D~)[row0 + i][k0 + kk], i < 64, kk < 16, four per thread
+  const SpecDev c0 = sa.curves[cbase];
+  const int n_s = c0.n_s;
+  const int NC = 2 * c0.km;
+  const double* __restrict__ D = sa.dpool + c0.dmat;
+  long long boff[CB];  // scalar offset of each curve's state block, -1 past the group
 #pragma unroll
-    for (int e = 0; e < 4; ++e) {
+  for (int cb = 0; cb < CB; ++cb)
+    boff[cb] = (cbase + cb < count) ? 2 * sa.curves[cbase + cb].off : -1;
+  double* As = lds;               // [BK][SA]
+  double* Bs = lds + BK * SA;     // [BK][SB]
+
+  double ra[AE], rb[BE];
+  // A tile element e of thread t: (i, kk) with i < 64, kk < BK; consecutive
+  // elements of a thread are consecutive in memory
+  auto a_index = [&](int e, int& i, int& kk) {
+    if constexpr (TRANS) {  // D~[k][i]: 64 consecutive i for each k
+      kk = t / (BM / AE);
+      i = (t % (BM / AE)) * AE + e;
+    } else {                // D~[i][k]: BK consecutive k for each i
+      i = t / (BK / AE);
+      kk = (t % (BK / AE)) * AE + e;
+    }
+  };
+  auto load = [&](int k0) {
+    // A tile: op(D~)[row0 + i][k0 + kk]
+#pragma unroll
+    for (int e = 0; e < AE; ++e) {
       int i, kk;
-      if constexpr (TRANS) {  // D~[k][i]: 64 consecutive i for each k
-        kk = (t >> 4);
-        i = ((t & 15) << 2) + e;
-      } else {                // D~[i][k]: 16 consecutive k for each i
-        i = t >> 2;
-        kk = ((t & 3) << 2) + e;
-      }
+      a_index(e, i, kk);
       const int gi = row0 + i, gk = k0 + kk;
       double v = 0.0;
       if (gi < n_s && gk < n_s) v = TRANS ? D[(long long)gk * n_s + gi] : D[(long long)gi * n_s + gk];
       ra[e] = v;
     }
+    // B tile: row k0 + kk of each curve's n_s x NC block, curves side by side
 #pragma unroll
     for (int e = 0; e < BE; ++e) {
       const int q = t + 256 * e;
-      const int kk = q / NCP, col = q % NCP;
+      const int kk = q / BW, rem = q % BW;
+      const int cb = rem / NCP, col = rem % NCP;
       const int gk = k0 + kk;
-      rb[e] = (gk < n_s && col < NC) ? double(B[(long long)gk * NC + col]) : 0.0;
+      long long o = -1;
+#pragma unroll
+      for (int x = 0; x < CB; ++x) o = (cb == x) ? boff[x] : o;
+      rb[e] = (gk < n_s && col < NC && o >= 0) ? double(sa.b[o + (long long)gk * NC + col]) : 0.0;
     }
   };
   auto store = [&]() {
 #pragma unroll
-    for (int e = 0; e < 4; ++e) {
+    for (int e = 0; e < AE; ++e) {
       int i, kk;
-      if constexpr (TRANS) {
-        kk = (t >> 4);
-        i = ((t & 15) << 2) + e;
-      } else {
-        i = t >> 2;
-        kk = ((t & 3) << 2) + e;
-      }
-      As[kk * BM + i] = ra[e];
+      a_index(e, i, kk);
+      As[kk * SA + i] = ra[e];
     }
 #pragma unroll
-    for (int e = 0; e < BE; ++e) Bs[t + 256 * e] = rb[e];  // [kk][col] with q = kk*NCP + col
+    for (int e = 0; e < BE; ++e) {
+      const int q = t + 256 * e;
+      Bs[(q / BW) * SB + q % BW] = rb[e];  // [kk][cb*NCP + col]
+    }
   };
 
-  acc_t acc[NT];
+  acc_t acc[NJ];
 #pragma unroll
-  for (int j = 0; j < NT; ++j) acc[j] = acc_t{0.0, 0.0, 0.0, 0.0};
+  for (int j = 0; j < NJ; ++j) acc[j] = acc_t{0.0, 0.0, 0.0, 0.0};
   load(0);
   for (int k0 = 0; k0 < n_s; k0 += BK) {
     __syncthreads();  // the previous step's reads of the tiles are done
@@ -291,49 +328,56 @@ __device__ __forceinline__ void spec_gemm_body(const SpecArgs<T>& sa, const Spec
 #pragma unroll
     for (int s = 0; s < BK / 4; ++s) {
       const int kk = 4 * s + (lane >> 4);
-      const double av = As[kk * BM + 16 * w + (lane & 15)];
+      const double av = As[kk * SA + 16 * w + (lane & 15)];
 #pragma unroll
-      for (int j = 0; j < NT; ++j) {
-        const double bv = Bs[kk * NCP + 16 * j + (lane & 15)];
+      for (int j = 0; j < NJ; ++j) {
+        const double bv = Bs[kk * SB + 16 * j + (lane & 15)];
         acc[j] = mma::mac(av, bv, acc[j]);
       }
     }
   }
 
-  // epilogue: element (row, col) of C, col = 2k + (0: re, 1: im); the
-  // product is rounded to the state dtype, the rest as in the row kernels
-  const double inv_S = cd.inv_S;
-  const bool act = (sa.active == nullptr) || sa.active[c] != 0;
-  const T sc = (EPI == EPI_GRAD && sa.scale != nullptr) ? T(sa.scale[c]) : T(1);
-  T* __restrict__ O = sa.out + 2 * cd.off;
+  // epilogue: element (row, col) of curve cb's C, col = 2k + (0: re, 1: im);
+  // the product is rounded to the state dtype, the rest as in the row kernels
 #pragma unroll
-  for (int j = 0; j < NT; ++j) {
-    const int col = 16 * j + (lane & 15);
-    const int k = col >> 1;
-    const bool im0 = (col == 1);
+  for (int cb = 0; cb < CB; ++cb) {
+    if (cbase + cb >= count) break;
+    const SpecDev cd = sa.curves[cbase + cb];
+    const int c = cd.c;
+    const double inv_S = cd.inv_S;
+    const bool act = (sa.active == nullptr) || sa.active[c] != 0;
+    const T sc = (EPI == EPI_GRAD && sa.scale != nullptr) ? T(sa.scale[c]) : T(1);
+    T* __restrict__ O = sa.out + 2 * cd.off;
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const int row = row0 + 16 * w + mma::row(lane, r);
-      if (row >= n_s || col >= NC) continue;
-      const long long idx = (long long)row * NC + col;
-      const T z = T(acc[j][r] * inv_S);
-      const bool interior = row >= 1 && row <= n_s - 2;
-      if constexpr (EPI == EPI_Y) {
-        O[idx] = z;
-      } else if constexpr (EPI == EPI_GRAD) {
-        const T pv = sa.p[2 * cd.off + idx];
-        const T f = sa.wlT[cd.row_off + row];
-        const T ck = (k == 0) ? T(1) : T(2);
-        O[idx] = (interior && !im0) ? (ck * sc) * fmaT(f, pv, -z) : T(0);
-      } else {
-        const T uv = sa.u[2 * cd.off + idx];
-        T o = uv;
-        if (interior && act) {
+    for (int jt = 0; jt < NT; ++jt) {
+      const int j = cb * NT + jt;
+      const int col = 16 * jt + (lane & 15);
+      const int k = col >> 1;
+      const bool im0 = (col == 1);
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row = row0 + 16 * w + mma::row(lane, r);
+        if (row >= n_s || col >= NC) continue;
+        const long long idx = (long long)row * NC + col;
+        const T z = T(acc[j][r] * inv_S);
+        const bool interior = row >= 1 && row <= n_s - 2;
+        if constexpr (EPI == EPI_Y) {
+          O[idx] = z;
+        } else if constexpr (EPI == EPI_GRAD) {
           const T pv = sa.p[2 * cd.off + idx];
           const T f = sa.wlT[cd.row_off + row];
-          o = fmaT(sa.pre[cd.mode_off + k], pv - z / f, uv);
+          const T ck = (k == 0) ? T(1) : T(2);
+          O[idx] = (interior && !im0) ? (ck * sc) * fmaT(f, pv, -z) : T(0);
+        } else {
+          const T uv = sa.u[2 * cd.off + idx];
+          T o = uv;
+          if (interior && act) {
+            const T pv = sa.p[2 * cd.off + idx];
+            const T f = sa.wlT[cd.row_off + row];
+            o = fmaT(sa.pre[cd.mode_off + k], pv - z / f, uv);
+          }
+          O[idx] = im0 ? T(0) : o;
         }
-        O[idx] = im0 ? T(0) : o;
       }
     }
   }
