@@ -160,6 +160,81 @@ def paper_shape_specs(n_curves: int = 64) -> list[CurveSpec]:
             for c in range(n_curves)]
 
 
+L22_EQUILIBRIA = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))),
+                              "tests", "golden", "L22_equilibria.npz")
+
+
+def l22_equilibrium(name: str) -> np.ndarray:
+    """Stored equilibrium of KS at L = 22, N_x = 64 (coefficients u_hat_k,
+    k = 0..21): "E0" (u = 0), "E1", "E2", "E3"; a suffix "+L/2" or "+L/4"
+    shifts it by that fraction of the period (u_hat_k e^{i q_k L/2}, ...)."""
+    base, _, shift = name.partition("+")
+    d = np.load(L22_EQUILIBRIA)
+    U = np.zeros(22, dtype=np.complex128) if base == "E0" else np.array(d[base])
+    if shift:
+        frac = {"L/2": 0.5, "L/4": 0.25, "L/3": 1.0 / 3.0, "L/6": 1.0 / 6.0}[shift]
+        V = U * np.exp(2j * np.pi * np.arange(U.size) * frac)
+        if np.all(U.real == 0):
+            # these shifts map each equilibrium to another copy that is
+            # inversion symmetric about x = 0: drop the rounding residue
+            assert np.abs(V.real).max() < 1e-12 * max(np.abs(V).max(), 1.0)
+            V = 1j * V.imag
+        U = V
+    return U
+
+
+def rational_s(n_s: int, S: float, s0: float = 0.0) -> np.ndarray:
+    """s_j = s0 + S cot(pi (1 - j / (n_s - 1))) on the rows (row 0: -inf)."""
+    th = np.pi * (1.0 - np.arange(n_s) / (n_s - 1))
+    with np.errstate(divide="ignore"):
+        s = s0 + S * np.cos(th) / np.sin(th)
+    s[0], s[-1] = -np.inf, np.inf
+    return s
+
+
+def l22_connection_curve(src: str, dst: str, n_s: int = 552, S: float = 55.0, s0: float = 0.0):
+    """The initial connecting curve of eq. KSE_initial_curve with a = 0 from
+    u_- = src to u_+ = dst on the rational grid:
+    u_0(s) = ((1 + tanh s) u_+ + (1 - tanh s) u_-) / 2 (end rows exactly u_-, u_+).
+    Returns (CurveSpec, U_hat [n_s, 22])."""
+    um, up = l22_equilibrium(src), l22_equilibrium(dst)
+    th = np.tanh(rational_s(n_s, S, s0))
+    U = 0.5 * ((1.0 + th)[:, None] * up[None, :] + (1.0 - th)[:, None] * um[None, :])
+    U[0], U[-1] = um, up
+    spec = CurveSpec(n_s, 64, 22.0, 0, 0.0, 0, 0.0, False, (22, 0), "rational", S, s0)
+    return spec, U
+
+
+# Connections of the paper's Table II (tab:parameters): row, from, to, M, S
+# (N = 64, s0 = 0, dtau = 0.01 for all).  Row 6 ends at E2 shifted by L/4.
+TABLE2 = [
+    (1, "E0", "E1", 80, 40.0), (2, "E0", "E2", 130, 35.0), (3, "E0", "E3", 120, 40.0),
+    (4, "E1", "E2", 550, 55.0), (5, "E1", "E3", 500, 60.0), (6, "E2", "E2+L/4", 400, 35.0),
+    (7, "E2", "E3", 450, 50.0), (8, "E3", "E2", 600, 50.0), (9, "E3", "E2", 500, 40.0),
+]
+# The destinations' other inversion-symmetric copies (about x = 0): E1 shifted
+# by L/2, E2 by L/4, E3 by L/6.
+OTHER_PHASE = {"E1": "E1+L/2", "E2": "E2+L/4", "E2+L/4": "E2", "E3": "E3+L/6", "E0": None}
+
+
+def table2_connections(both_phases: bool = True):
+    """Initial curves (eq. KSE_initial_curve, a = 0) for the rows of Table II:
+    a list of (label, CurveSpec, U_hat).  With both_phases, every row whose
+    destination has another inversion-symmetric copy appears once more with
+    that copy (the table does not print the relative phase; rows from E0 have
+    no distinct phases).  Row 6 with a = 0 is the run the paper reports stuck
+    at a local minimum."""
+    out = []
+    for row, a, b, M, S in TABLE2:
+        # E0 is translation invariant (every phase of the destination is
+        # equivalent), and row 6 connects E2 to its own shifted copy
+        other = OTHER_PHASE.get(b) if (both_phases and a != "E0" and row != 6) else None
+        for dst in ([b, other] if other else [b]):
+            spec, U = l22_connection_curve(a, dst, M + 2, S)
+            out.append((f"row{row}:{a}->{dst}", spec, U))
+    return out
+
+
 def round_to(U: np.ndarray, dtype) -> np.ndarray:
     """Round complex128 data to the run precision (complex64 for FP32) and back."""
     if np.dtype(dtype) == np.float32:

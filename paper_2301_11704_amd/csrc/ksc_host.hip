@@ -269,6 +269,12 @@ struct ksc_problem {
     int nx, first, count, n_s;
   };
   std::vector<SpecGroup> spec_groups;
+  // one product launch per n_x over its groups (device table d_sgroups)
+  struct SpecLaunch {
+    int nx, gfirst, ngroups, n_blocks;
+  };
+  std::vector<SpecLaunch> spec_launches;
+  ksc::SpecGroupDev* d_sgroups = nullptr;
   void* d_Y = nullptr;
   void* d_WR = nullptr;
   void* d_P = nullptr;
@@ -618,24 +624,24 @@ ksc_status launch_post(ksc_problem* p, int mode, const void* in, void* out, cons
 
 // ------------------------------------------------------- spectral d/ds --
 
-hipError_t spec_gemm(int nx, int epi, int n_s, int count, hipStream_t s,
+hipError_t spec_gemm(int nx, int epi, const ksc::SpecGroupDev* g, int ng, int nb, hipStream_t s,
                      const ksc::SpecArgs<float>& a, hipEvent_t e0, hipEvent_t e1) {
   switch (nx) {
-    case 8: return ksc::launch_spec_gemm_f32_8(epi, n_s, count, s, a, e0, e1);
-    case 16: return ksc::launch_spec_gemm_f32_16(epi, n_s, count, s, a, e0, e1);
-    case 32: return ksc::launch_spec_gemm_f32_32(epi, n_s, count, s, a, e0, e1);
-    case 64: return ksc::launch_spec_gemm_f32_64(epi, n_s, count, s, a, e0, e1);
-    case 128: return ksc::launch_spec_gemm_f32_128(epi, n_s, count, s, a, e0, e1);
+    case 8: return ksc::launch_spec_gemm_f32_8(epi, g, ng, nb, s, a, e0, e1);
+    case 16: return ksc::launch_spec_gemm_f32_16(epi, g, ng, nb, s, a, e0, e1);
+    case 32: return ksc::launch_spec_gemm_f32_32(epi, g, ng, nb, s, a, e0, e1);
+    case 64: return ksc::launch_spec_gemm_f32_64(epi, g, ng, nb, s, a, e0, e1);
+    case 128: return ksc::launch_spec_gemm_f32_128(epi, g, ng, nb, s, a, e0, e1);
     default: return hipErrorInvalidValue;
   }
 }
-hipError_t spec_gemm(int nx, int epi, int n_s, int count, hipStream_t s,
+hipError_t spec_gemm(int nx, int epi, const ksc::SpecGroupDev* g, int ng, int nb, hipStream_t s,
                      const ksc::SpecArgs<double>& a, hipEvent_t e0, hipEvent_t e1) {
   switch (nx) {
-    case 8: return ksc::launch_spec_gemm_f64_8(epi, n_s, count, s, a, e0, e1);
-    case 16: return ksc::launch_spec_gemm_f64_16(epi, n_s, count, s, a, e0, e1);
-    case 32: return ksc::launch_spec_gemm_f64_32(epi, n_s, count, s, a, e0, e1);
-    case 64: return ksc::launch_spec_gemm_f64_64(epi, n_s, count, s, a, e0, e1);
+    case 8: return ksc::launch_spec_gemm_f64_8(epi, g, ng, nb, s, a, e0, e1);
+    case 16: return ksc::launch_spec_gemm_f64_16(epi, g, ng, nb, s, a, e0, e1);
+    case 32: return ksc::launch_spec_gemm_f64_32(epi, g, ng, nb, s, a, e0, e1);
+    case 64: return ksc::launch_spec_gemm_f64_64(epi, g, ng, nb, s, a, e0, e1);
     default: return hipErrorInvalidValue;
   }
 }
@@ -669,7 +675,7 @@ ksc_status launch_spectral(ksc_problem* p, int mode, const void* in, void* out,
                            const double* scale, const uint8_t* active, hipStream_t s,
                            const hipEvent_t* ev) {
   const int W = p->W;
-  const int ng = int(p->spec_groups.size());
+  const int nl = int(p->spec_launches.size());
   hipEvent_t e_first = ev ? ev[0] : nullptr, e_last = ev ? ev[1] : nullptr;
   ksc::SpecArgs<T> ga{};
   ga.dpool = static_cast<const double*>(p->d_dpool);
@@ -677,15 +683,15 @@ ksc_status launch_spectral(ksc_problem* p, int mode, const void* in, void* out,
   ga.pre = static_cast<const T*>(p->d_pre);
   ga.scale = scale;
   ga.active = active;
+  ga.curves = p->d_spec;
   // 1. Y = D_t U
-  for (int g = 0; g < ng; ++g) {
-    const auto& G = p->spec_groups[g];
+  for (int l = 0; l < nl; ++l) {
+    const auto& G = p->spec_launches[l];
     ksc::SpecArgs<T> a = ga;
-    a.curves = p->d_spec + G.first;
     a.b = static_cast<const T*>(in);
     a.out = static_cast<T*>(p->d_Y);
-    hipError_t e = spec_gemm(G.nx, ksc::EPI_Y, G.n_s, G.count, s, a, g == 0 ? e_first : nullptr,
-                             nullptr);
+    hipError_t e = spec_gemm(G.nx, ksc::EPI_Y, p->d_sgroups + G.gfirst, G.ngroups, G.n_blocks, s, a,
+                             l == 0 ? e_first : nullptr, nullptr);
     if (e != hipSuccess) return fail(KSC_ERR_HIP, std::string("spectral product: ") + hipGetErrorString(e));
   }
   // 2. rows: residual, cost partials, row-local adjoint part
@@ -713,16 +719,16 @@ ksc_status launch_spectral(ksc_problem* p, int mode, const void* in, void* out,
   }
   if (mode == ksc::MODE_J) return KSC_OK;
   // 3. Z' = D_t^T (2 w L r_hat) and the output
-  for (int g = 0; g < ng; ++g) {
-    const auto& G = p->spec_groups[g];
+  for (int l = 0; l < nl; ++l) {
+    const auto& G = p->spec_launches[l];
     ksc::SpecArgs<T> a = ga;
-    a.curves = p->d_spec + G.first;
     a.b = static_cast<const T*>(p->d_WR);
     a.p = static_cast<const T*>(p->d_P);
     a.u = static_cast<const T*>(in);
     a.out = static_cast<T*>(out);
-    hipError_t e = spec_gemm(G.nx, mode == ksc::MODE_GRAD ? ksc::EPI_GRAD : ksc::EPI_STEP, G.n_s,
-                             G.count, s, a, nullptr, g == ng - 1 ? e_last : nullptr);
+    hipError_t e = spec_gemm(G.nx, mode == ksc::MODE_GRAD ? ksc::EPI_GRAD : ksc::EPI_STEP,
+                             p->d_sgroups + G.gfirst, G.ngroups, G.n_blocks, s, a, nullptr,
+                             l == nl - 1 ? e_last : nullptr);
     if (e != hipSuccess) return fail(KSC_ERR_HIP, std::string("spectral product: ") + hipGetErrorString(e));
   }
   return KSC_OK;
@@ -806,6 +812,22 @@ ksc_status setup_spectral(ksc_problem* p) {
   }
   KSC_HIP(hipMalloc(&p->d_spec, sd.size() * sizeof(SpecDev)));
   KSC_HIP(hipMemcpy(p->d_spec, sd.data(), sd.size() * sizeof(SpecDev), hipMemcpyHostToDevice));
+  // product launches: one per n_x, its groups' workgroups laid end to end
+  std::vector<ksc::SpecGroupDev> gd;
+  p->spec_launches.clear();
+  for (const auto& G : p->spec_groups) {
+    if (p->spec_launches.empty() || p->spec_launches.back().nx != G.nx)
+      p->spec_launches.push_back({G.nx, int(gd.size()), 0, 0});
+    auto& Lh = p->spec_launches.back();
+    const int cb = ksc::spec_curves_per_block(G.nx);
+    const int rb = (G.n_s + ksc::kSpecRowsPerBlock - 1) / ksc::kSpecRowsPerBlock;
+    gd.push_back({G.first, G.count, rb, Lh.n_blocks});
+    Lh.ngroups++;
+    Lh.n_blocks += rb * ((G.count + cb - 1) / cb);
+  }
+  KSC_HIP(hipMalloc(&p->d_sgroups, gd.size() * sizeof(ksc::SpecGroupDev)));
+  KSC_HIP(hipMemcpy(p->d_sgroups, gd.data(), gd.size() * sizeof(ksc::SpecGroupDev),
+                    hipMemcpyHostToDevice));
   KSC_HIP(hipMalloc(&p->d_Y, p->state_bytes()));
   KSC_HIP(hipMalloc(&p->d_WR, p->state_bytes()));
   KSC_HIP(hipMalloc(&p->d_P, p->state_bytes()));
@@ -1090,7 +1112,7 @@ ksc_status ksc_destroy(ksc_problem* p) {
   void* bufs[] = {p->d_bounds, p->d_cd,  p->d_tiles, p->d_cs,    p->d_wlT,    p->d_wlD,
                   p->d_A,   p->d_pre,   p->d_sqrtL, p->d_part,   p->d_prevJ2,
                   p->d_flags, p->d_J2,  p->d_edge,  p->d_dpool,  p->d_spec,  p->d_Y,
-                  p->d_WR,  p->d_P};
+                  p->d_WR,  p->d_P,   p->d_sgroups};
   for (void* b : bufs)
     if (b) hipFree(b);
   delete p;

@@ -20,11 +20,18 @@ constexpr bool spec_supported() {
   return NX * int(sizeof(T)) <= 512;
 }
 
-// epi: EPI_Y (Y = D_t B), EPI_GRAD or EPI_STEP (with op(D~) = D~^T) over a
-// group of `count` curves (a.curves) that share n_x and n_s.
+// Curves per workgroup of the products (ksc_spec.hpp spec_cb) for n_x.
+constexpr int spec_curves_per_block(int nx) {
+  return (spec_ncp(nx) / 16) >= 3 ? 1 : (spec_ncp(nx) / 16) == 2 ? 2 : 3;
+}
+
+// epi: EPI_Y (Y = D_t B), EPI_GRAD or EPI_STEP (with op(D~) = D~^T) over the
+// n_groups groups (device table) of curves with this n_x, n_blocks workgroups
+// in all; a.curves is the SpecDev array the groups index.
 #define KSC_DECLARE_SPEC(TNAME, T, NX)                                                          \
-  hipError_t launch_spec_gemm_##TNAME##_##NX(int epi, int n_s, int count, hipStream_t s,        \
-                                             const SpecArgs<T>& a, hipEvent_t e0, hipEvent_t e1); \
+  hipError_t launch_spec_gemm_##TNAME##_##NX(int epi, const SpecGroupDev* groups, int n_groups,  \
+                                             int n_blocks, hipStream_t s, const SpecArgs<T>& a,  \
+                                             hipEvent_t e0, hipEvent_t e1);                      \
   hipError_t launch_spec_row_##TNAME##_##NX(int W, int mode, int grid, size_t lds, hipStream_t s, \
                                             const SpecRowArgs<T>& a, hipEvent_t e0, hipEvent_t e1);
 KSC_DECLARE_SPEC(f32, float, 8)

@@ -12,13 +12,23 @@
 
 namespace ksc {
 
-// grid.x: row blocks of 64, grid.y: blocks of spec_cb<NCP>() curves of one
-// group (curves sharing n_x and n_s); `count` curves in the group.
+// One workgroup per (group, row block of 64, block of spec_cb<NCP>() curves)
+// over all the groups of one n_x (a group: curves that share n_s); the
+// workgroup finds its group in the small group table.
 template <typename T, int NCP, bool TRANS, int EPI>
-__global__ __launch_bounds__(256) void spec_gemm_kernel(SpecArgs<T> sa, int count) {
+__global__ __launch_bounds__(256) void spec_gemm_kernel(SpecArgs<T> sa,
+                                                        const SpecGroupDev* __restrict__ groups,
+                                                        int n_groups) {
   __shared__ __align__(16) double lds[spec_gemm_lds<NCP>()];
-  spec_gemm_body<T, NCP, TRANS, EPI>(sa, count, int(blockIdx.y) * spec_cb<NCP>(),
-                                     int(blockIdx.x) * kSpecRowsPerBlock, lds);
+  const int bid = blockIdx.x;
+  int g = 0;
+  while (g + 1 < n_groups && bid >= groups[g + 1].block0) ++g;  // uniform over the workgroup
+  const SpecGroupDev G = groups[g];
+  const int local = bid - G.block0;
+  SpecArgs<T> ga = sa;
+  ga.curves = sa.curves + G.first;
+  spec_gemm_body<T, NCP, TRANS, EPI>(ga, G.count, (local / G.row_blocks) * spec_cb<NCP>(),
+                                     (local % G.row_blocks) * kSpecRowsPerBlock, lds);
 }
 
 template <int NX, typename T, int W, int MODE>
@@ -70,23 +80,23 @@ hipError_t KSC_CAT(KSC_CAT(KSC_CAT(launch_spec_row_, KSC_TNAME), _), KSC_NX)(
 }
 
 hipError_t KSC_CAT(KSC_CAT(KSC_CAT(launch_spec_gemm_, KSC_TNAME), _), KSC_NX)(
-    int epi, int n_s, int count, hipStream_t s, const SpecArgs<KSC_T>& a, hipEvent_t e0,
-    hipEvent_t e1) {
+    int epi, const SpecGroupDev* groups, int n_groups, int n_blocks, hipStream_t s,
+    const SpecArgs<KSC_T>& a, hipEvent_t e0, hipEvent_t e1) {
   constexpr int NCP = spec_ncp(KSC_NX);
-  constexpr int CB = spec_cb<NCP>();
-  const dim3 grid((n_s + kSpecRowsPerBlock - 1) / kSpecRowsPerBlock, (count + CB - 1) / CB);
+  static_assert(spec_curves_per_block(KSC_NX) == spec_cb<NCP>(), "host and kernel blocking agree");
+  const dim3 grid(n_blocks);
   if constexpr (!spec_supported<KSC_NX, KSC_T>()) {
     return hipErrorInvalidValue;
   } else {
     switch (epi) {
       case EPI_Y:
-        hipExtLaunchKernelGGL((spec_gemm_kernel<KSC_T, NCP, false, EPI_Y>), grid, dim3(256), 0, s, e0, e1, 0, a, count);
+        hipExtLaunchKernelGGL((spec_gemm_kernel<KSC_T, NCP, false, EPI_Y>), grid, dim3(256), 0, s, e0, e1, 0, a, groups, n_groups);
         break;
       case EPI_GRAD:
-        hipExtLaunchKernelGGL((spec_gemm_kernel<KSC_T, NCP, true, EPI_GRAD>), grid, dim3(256), 0, s, e0, e1, 0, a, count);
+        hipExtLaunchKernelGGL((spec_gemm_kernel<KSC_T, NCP, true, EPI_GRAD>), grid, dim3(256), 0, s, e0, e1, 0, a, groups, n_groups);
         break;
       default:
-        hipExtLaunchKernelGGL((spec_gemm_kernel<KSC_T, NCP, true, EPI_STEP>), grid, dim3(256), 0, s, e0, e1, 0, a, count);
+        hipExtLaunchKernelGGL((spec_gemm_kernel<KSC_T, NCP, true, EPI_STEP>), grid, dim3(256), 0, s, e0, e1, 0, a, groups, n_groups);
         break;
     }
     return hipGetLastError();

@@ -51,6 +51,15 @@ struct SpecArgs {
 
 enum SpecEpi : int { EPI_Y = 0, EPI_GRAD = 1, EPI_STEP = 2 };
 
+// A group of curves that share n_x and n_s (one D~), as one launch sees it:
+// its workgroups are [block0, block0 + row_blocks * curve_blocks).
+struct SpecGroupDev {
+  int first;       // first curve (index into the SpecDev array)
+  int count;       // curves in the group
+  int row_blocks;  // ceil(n_s / 64)
+  int block0;      // first workgroup of the group in the launch
+};
+
 // Row kernel arguments: the tile machinery's KernelArgs (state in a.in, tiles,
 // tables, partials) plus the derivative rows Y and the two output arrays.
 template <typename T>

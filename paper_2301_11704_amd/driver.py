@@ -35,6 +35,7 @@ class DescentLog:
     dtau: float = 0.0
     dtype: str = "f32"
     J_history: list = field(default_factory=list)  # (step, [J per curve])
+    Jarc_history: list = field(default_factory=list)  # (step, [J_arc per curve]) with a J_arc target
     events: list = field(default_factory=list)     # (step, text)
     converged: np.ndarray | None = None
 
@@ -156,6 +157,10 @@ def descend_to(backend, dtau: float, J_target: float = 1e-8, max_steps: int = 10
         log.tau += n * dtau
         log.dtau = dtau
         log.J_history.append((log.steps, Jn.copy()))
+        Ja = None
+        if Jarc_target is not None:
+            Ja = backend.J_arc()
+            log.Jarc_history.append((log.steps, Ja.copy()))
         if progress is not None:
             progress(log, Jn)
         improved = Jn < best * (1 - 1e-7)
@@ -164,8 +169,8 @@ def descend_to(backend, dtau: float, J_target: float = 1e-8, max_steps: int = 10
         J_prev = Jn
         last_good = backend.snapshot()
         done = Jn < J_target
-        if Jarc_target is not None:
-            done = done | (backend.J_arc() < Jarc_target)
+        if Ja is not None:
+            done = done | (Ja < Jarc_target)
         newly = done & active
         if np.any(newly):
             log.events.append((log.steps, f"converged: {np.flatnonzero(newly).tolist()}"))
@@ -195,7 +200,10 @@ def descend_to(backend, dtau: float, J_target: float = 1e-8, max_steps: int = 10
 def main(argv=None):
     """Descend the batched workload-4 curves (stored KS-trajectory endpoints,
     L = 66, N_x = 128) to a target J, FP32 first and FP64 to finish, printing
-    one progress line per chunk."""
+    one progress line per chunk.  With --connection, descend instead the
+    initial curves of eq. KSE_initial_curve (a = 0) between stored L = 22
+    equilibria, e.g. E1-E2 (the paper's first run: N_x = 64, N_s = 552,
+    S = 55, dtau = 0.01, spectral d/ds, stop at J_arc < 1e-12)."""
     import argparse
     import sys
     import time
@@ -213,15 +221,54 @@ def main(argv=None):
     ap.add_argument("--every", type=int, default=500)
     ap.add_argument("--chunk", type=int, default=50_000)
     ap.add_argument("--checkpoint", default=None)
+    ap.add_argument("--checkpoint-every", type=int, default=None, help="steps between checkpoints")
     ap.add_argument("--resume", action="store_true")
+    ap.add_argument("--connection", default=None,
+                    help="comma-separated SRC-DST pairs of L = 22 equilibria, e.g. E1-E2,E1-E2+L/4")
+    ap.add_argument("--table2", action="store_true",
+                    help="the connections of the paper's Table II with their M and S, both "
+                         "relative phases where they differ (implies the --connection defaults)")
+    ap.add_argument("--ds", default=None, choices=["stencil", "spectral"],
+                    help="d/ds (default: spectral with --connection, else stencil)")
+    ap.add_argument("--S", type=float, default=55.0, help="rational map scale (--connection)")
+    ap.add_argument("--dtype", default=None, choices=["f32", "f64"],
+                    help="start precision (default: f64 with --connection, else f32)")
+    ap.add_argument("--jarc-target", type=float, default=None,
+                    help="also stop a curve when J_arc falls below this (--connection: 1e-12)")
+    ap.add_argument("--history", default=None,
+                    help="write the J and J_arc records (per chunk) and the events to this JSON file")
     args = ap.parse_args(argv)
 
     import ksinputs
     from . import CurveDesc, Problem
 
-    specs, Us = ksinputs.config4_curves(args.curves, args.n_s)
+    labels = None
+    if args.table2:
+        made = ksinputs.table2_connections()
+        labels = [m[0] for m in made]
+        specs, Us = [m[1] for m in made], [m[2] for m in made]
+        args.connection = "table2"
+    elif args.connection:
+        pairs = [p.split("-", 1) for p in args.connection.split(",")]
+        n_s = args.n_s if args.n_s != 1024 else 552
+        made = [ksinputs.l22_connection_curve(a, b, n_s, args.S) for a, b in pairs]
+        specs, Us = [m[0] for m in made], [m[1] for m in made]
+        labels = [p for p in args.connection.split(",")]
+    if args.connection:
+        ds = args.ds or "spectral"
+        dt = torch.float64 if (args.dtype or "f64") == "f64" else torch.float32
+        if args.dtau == 5e-4:
+            args.dtau = 0.01
+        if args.jarc_target is None:
+            args.jarc_target = 1e-12
+        if args.target == 1e-8:
+            args.target = 0.0
+    else:
+        specs, Us = ksinputs.config4_curves(args.curves, args.n_s)
+        ds = args.ds or "stencil"
+        dt = torch.float64 if args.dtype == "f64" else torch.float32
     prob = Problem([CurveDesc(s.n_s, s.n_x, s.L, s.map, s.scale, s.s0) for s in specs],
-                   dtype=torch.float32)
+                   dtype=dt, ds=ds)
     prob.tune(None)
     X = prob.new_state()
     for c, U in enumerate(Us):
@@ -229,24 +276,52 @@ def main(argv=None):
     b = GpuBackend(prob, X)
     t0 = time.time()
     J0 = np.sqrt(b.J2())
-    print(f"start: {args.curves} curves, J max {J0.max():.3e} min {J0.min():.3e}", flush=True)
+    print(f"start: {len(specs)} curves ({ds} d/ds), J max {J0.max():.3e} min {J0.min():.3e}"
+          + (f", J_arc {np.array2string(b.J_arc(), precision=3)}" if args.jarc_target else ""),
+          flush=True)
 
     def report(log, J):
+        arc = ""
+        if log.Jarc_history and log.Jarc_history[-1][0] == log.steps:
+            arc = " J_arc " + np.array2string(log.Jarc_history[-1][1], precision=3)
         print(f"step {log.steps:9d} tau {log.tau:10.3f} {log.dtype} dtau {log.dtau:.2e} "
-              f"J max {np.max(J):.3e} min {np.min(J):.3e} converged {int(np.sum(J < args.target))}"
+              f"J max {np.max(J):.3e} min {np.min(J):.3e}{arc}"
               f" wall {time.time() - t0:7.1f}s", flush=True)
 
     b2, log = descend_to(b, dtau=args.dtau, J_target=args.target, max_steps=args.max_steps,
                          every=args.every, chunk=args.chunk, switch_J=args.switch,
                          stall_records=args.stall_records, checkpoint=args.checkpoint,
-                         resume=args.resume, progress=report)
+                         checkpoint_every=args.checkpoint_every, resume=args.resume,
+                         progress=report, Jarc_target=args.jarc_target)
     J = np.sqrt(np.abs(b2.J2()))
+    ok = J < args.target
+    if args.jarc_target is not None:
+        Ja = b2.J_arc()
+        ok = ok | (Ja < args.jarc_target)
+        print(f"J_arc {np.array2string(Ja, precision=3)}", flush=True)
+        if labels:
+            first = {}
+            for st, a in log.Jarc_history:
+                for i in np.flatnonzero(a < args.jarc_target):
+                    first.setdefault(int(i), st)
+            for i, lab in enumerate(labels):
+                when = f"tau {first[i] * args.dtau:.0f}" if i in first else "not converged"
+                print(f"  {lab:24s} N_s {specs[i].n_s:4d} S {specs[i].scale:4.0f} "
+                      f"J_arc {Ja[i]:.3e}  {when}", flush=True)
     print(f"done: steps {log.steps} tau {log.tau:.3f} dtype {log.dtype} J max {J.max():.3e} "
-          f"converged {int(np.sum(J < args.target))}/{len(J)} wall {time.time() - t0:.1f}s",
-          flush=True)
+          f"converged {int(np.sum(ok))}/{len(J)} wall {time.time() - t0:.1f}s", flush=True)
     for st, ev in log.events[-10:]:
         print(f"  event at step {st}: {ev}", flush=True)
-    return 0 if np.all(J < args.target) else 1
+    if args.history:
+        arc = dict((st, list(map(float, a))) for st, a in log.Jarc_history)
+        with open(args.history, "w") as fh:
+            json.dump({"curves": [f"{sp.n_x}x{sp.n_s} L={sp.L} S={sp.scale}" for sp in specs],
+                       "labels": labels,
+                       "connection": args.connection, "ds": ds, "dtau0": args.dtau,
+                       "records": [{"step": st, "tau": st * args.dtau, "J": list(map(float, j)),
+                                    "J_arc": arc.get(st)} for st, j in log.J_history],
+                       "events": log.events}, fh)
+    return 0 if np.all(ok) else 1
 
 
 if __name__ == "__main__":

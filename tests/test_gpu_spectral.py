@@ -211,3 +211,26 @@ def test_spectral_autograd_matches_eval_grad_and_is_deterministic():
     torch.cuda.synchronize()
     assert torch.equal(G, G2)
     assert torch.allclose(Xr.grad, 3.0 * G, rtol=1e-14, atol=0)
+
+
+def test_spectral_descent_from_E1_to_E2_matches_oracle():
+    """The paper's first connection (E1 -> E2, N_x = 64, N_s = 552, S = 55,
+    dtau = 0.01) for 60 steps in FP64 against 60 oracle steps."""
+    spec, U = ksinputs.l22_connection_curve("E1", "E2")
+    prob = _problem([spec], np.float64)
+    X = prob.new_state()
+    prob.upload(X, 0, U)
+    tr = prob.descend(X, 60, 0.01, every=20)
+    torch.cuda.synchronize()
+    c = _curve(spec)
+    Ur = U.copy()
+    Jr = []
+    for _ in range(60):
+        Jr.append(oracle.J2(c, Ur))
+        Ur = oracle.step(c, Ur, 0.01)
+    # per-step rounding differences of at most 1e-12 add up over 60 steps
+    got = prob.download(X, 0)
+    assert np.linalg.norm(got - Ur) / np.linalg.norm(Ur) <= 60 * TOL[np.float64]
+    trc = tr.cpu().numpy()[:, 0]
+    for g in range(3):
+        assert abs(trc[g] - Jr[20 * g + 19]) <= 60 * TOL[np.float64] * Jr[20 * g + 19]

@@ -73,3 +73,24 @@ def test_equilibria_symmetries_and_newton():
         U2, res = equilibrium(n_x, L, U[1:].imag)
         assert res < 1e-12 and np.abs(U2 - U).max() < 1e-12
         assert np.linalg.norm(f_odd(c, U[1:].imag)) < 1e-12
+
+
+def test_initial_curve_and_spectral_descent_from_E1_to_E2():
+    """The initial curve of eq. KSE_initial_curve (a = 0) between the stored
+    E1 and E2 on the paper's grid (N_x = 64, M = 550, S = 55) has the
+    equilibria as its end rows and stays in the inversion-symmetric subspace;
+    with the spectral d/ds the semi-implicit step at the paper's dtau = 0.01
+    decreases J^2 monotonically (the paper reports this step as stable)."""
+    import ksinputs
+    spec, U = ksinputs.l22_connection_curve("E1", "E2")
+    assert spec.n_s == 552 and spec.n_x == 64 and spec.scale == 55.0
+    E1, E2 = ksinputs.l22_equilibrium("E1"), ksinputs.l22_equilibrium("E2")
+    assert np.array_equal(U[0], E1) and np.array_equal(U[-1], E2)
+    assert np.all(U.real == 0)
+    c = oracle.Curve(spec.n_s, spec.n_x, spec.L, "rational", spec.scale, ds="spectral")
+    J = [oracle.J2(c, U)]
+    for _ in range(60):
+        U = oracle.step(c, U, 0.01)
+        J.append(oracle.J2(c, U))
+    assert np.all(np.diff(J) < 0) and J[-1] < 0.6 * J[0]
+    assert np.abs(U.real).max() < 1e-12  # the descent keeps the subspace
