@@ -272,9 +272,12 @@ struct ksc_problem {
   // one product launch per n_x over its groups (device table d_sgroups)
   struct SpecLaunch {
     int nx, gfirst, ngroups, n_blocks;
+    int kparts;  // parts of the k range (small launches split k to fill the chip)
+    int nk_max;  // k steps of the group with the largest n_s
   };
   std::vector<SpecLaunch> spec_launches;
   ksc::SpecGroupDev* d_sgroups = nullptr;
+  double* d_kpart = nullptr;  // split-k partial products: [max kparts][state scalars]
   void* d_Y = nullptr;
   void* d_WR = nullptr;
   void* d_P = nullptr;
@@ -322,8 +325,9 @@ int rows_per_tile(const ksc_problem* p, int W, int nx) { return 64 * W / lanes_p
 // LDS staging buffer of one tile: rows j0-1 .. j0+R, 16 bytes of alignment slack.
 size_t lds_for(const ksc_problem* p, int W, int nx) {
   if (p->spectral()) {  // state rows and d/ds rows of the tile, each with slack
-    const size_t cs = 2 * p->esize(), E = 16 / cs;
-    return 2 * (size_t(rows_per_tile(p, W, nx)) * modes_of(nx) + 2 * E) * cs;
+    const size_t cs = p->elem_bytes(), E = 16 / cs;
+    const size_t per_row = p->odd() ? modes_of(nx) - 1 : modes_of(nx);
+    return 2 * (size_t(rows_per_tile(p, W, nx)) * per_row + 2 * E) * cs;
   }
   // (odd subspace: the last 16-byte chunk of a staged block may start up to
   // 16 bytes past the block and end 16 bytes after that)
@@ -624,45 +628,45 @@ ksc_status launch_post(ksc_problem* p, int mode, const void* in, void* out, cons
 
 // ------------------------------------------------------- spectral d/ds --
 
-hipError_t spec_gemm(int nx, int epi, const ksc::SpecGroupDev* g, int ng, int nb, hipStream_t s,
-                     const ksc::SpecArgs<float>& a, hipEvent_t e0, hipEvent_t e1) {
+hipError_t spec_gemm(int nx, int odd, int epi, const ksc::SpecGroupDev* g, int ng, int nb,
+                     hipStream_t s, const ksc::SpecArgs<float>& a, hipEvent_t e0, hipEvent_t e1) {
   switch (nx) {
-    case 8: return ksc::launch_spec_gemm_f32_8(epi, g, ng, nb, s, a, e0, e1);
-    case 16: return ksc::launch_spec_gemm_f32_16(epi, g, ng, nb, s, a, e0, e1);
-    case 32: return ksc::launch_spec_gemm_f32_32(epi, g, ng, nb, s, a, e0, e1);
-    case 64: return ksc::launch_spec_gemm_f32_64(epi, g, ng, nb, s, a, e0, e1);
-    case 128: return ksc::launch_spec_gemm_f32_128(epi, g, ng, nb, s, a, e0, e1);
+    case 8: return ksc::launch_spec_gemm_f32_8(odd, epi, g, ng, nb, s, a, e0, e1);
+    case 16: return ksc::launch_spec_gemm_f32_16(odd, epi, g, ng, nb, s, a, e0, e1);
+    case 32: return ksc::launch_spec_gemm_f32_32(odd, epi, g, ng, nb, s, a, e0, e1);
+    case 64: return ksc::launch_spec_gemm_f32_64(odd, epi, g, ng, nb, s, a, e0, e1);
+    case 128: return ksc::launch_spec_gemm_f32_128(odd, epi, g, ng, nb, s, a, e0, e1);
     default: return hipErrorInvalidValue;
   }
 }
-hipError_t spec_gemm(int nx, int epi, const ksc::SpecGroupDev* g, int ng, int nb, hipStream_t s,
-                     const ksc::SpecArgs<double>& a, hipEvent_t e0, hipEvent_t e1) {
+hipError_t spec_gemm(int nx, int odd, int epi, const ksc::SpecGroupDev* g, int ng, int nb,
+                     hipStream_t s, const ksc::SpecArgs<double>& a, hipEvent_t e0, hipEvent_t e1) {
   switch (nx) {
-    case 8: return ksc::launch_spec_gemm_f64_8(epi, g, ng, nb, s, a, e0, e1);
-    case 16: return ksc::launch_spec_gemm_f64_16(epi, g, ng, nb, s, a, e0, e1);
-    case 32: return ksc::launch_spec_gemm_f64_32(epi, g, ng, nb, s, a, e0, e1);
-    case 64: return ksc::launch_spec_gemm_f64_64(epi, g, ng, nb, s, a, e0, e1);
+    case 8: return ksc::launch_spec_gemm_f64_8(odd, epi, g, ng, nb, s, a, e0, e1);
+    case 16: return ksc::launch_spec_gemm_f64_16(odd, epi, g, ng, nb, s, a, e0, e1);
+    case 32: return ksc::launch_spec_gemm_f64_32(odd, epi, g, ng, nb, s, a, e0, e1);
+    case 64: return ksc::launch_spec_gemm_f64_64(odd, epi, g, ng, nb, s, a, e0, e1);
     default: return hipErrorInvalidValue;
   }
 }
-hipError_t spec_row(int nx, int W, int mode, int grid, size_t lds, hipStream_t s,
+hipError_t spec_row(int nx, int odd, int W, int mode, int grid, size_t lds, hipStream_t s,
                     const ksc::SpecRowArgs<float>& a, hipEvent_t e0, hipEvent_t e1) {
   switch (nx) {
-    case 8: return ksc::launch_spec_row_f32_8(W, mode, grid, lds, s, a, e0, e1);
-    case 16: return ksc::launch_spec_row_f32_16(W, mode, grid, lds, s, a, e0, e1);
-    case 32: return ksc::launch_spec_row_f32_32(W, mode, grid, lds, s, a, e0, e1);
-    case 64: return ksc::launch_spec_row_f32_64(W, mode, grid, lds, s, a, e0, e1);
-    case 128: return ksc::launch_spec_row_f32_128(W, mode, grid, lds, s, a, e0, e1);
+    case 8: return ksc::launch_spec_row_f32_8(odd, W, mode, grid, lds, s, a, e0, e1);
+    case 16: return ksc::launch_spec_row_f32_16(odd, W, mode, grid, lds, s, a, e0, e1);
+    case 32: return ksc::launch_spec_row_f32_32(odd, W, mode, grid, lds, s, a, e0, e1);
+    case 64: return ksc::launch_spec_row_f32_64(odd, W, mode, grid, lds, s, a, e0, e1);
+    case 128: return ksc::launch_spec_row_f32_128(odd, W, mode, grid, lds, s, a, e0, e1);
     default: return hipErrorInvalidValue;
   }
 }
-hipError_t spec_row(int nx, int W, int mode, int grid, size_t lds, hipStream_t s,
+hipError_t spec_row(int nx, int odd, int W, int mode, int grid, size_t lds, hipStream_t s,
                     const ksc::SpecRowArgs<double>& a, hipEvent_t e0, hipEvent_t e1) {
   switch (nx) {
-    case 8: return ksc::launch_spec_row_f64_8(W, mode, grid, lds, s, a, e0, e1);
-    case 16: return ksc::launch_spec_row_f64_16(W, mode, grid, lds, s, a, e0, e1);
-    case 32: return ksc::launch_spec_row_f64_32(W, mode, grid, lds, s, a, e0, e1);
-    case 64: return ksc::launch_spec_row_f64_64(W, mode, grid, lds, s, a, e0, e1);
+    case 8: return ksc::launch_spec_row_f64_8(odd, W, mode, grid, lds, s, a, e0, e1);
+    case 16: return ksc::launch_spec_row_f64_16(odd, W, mode, grid, lds, s, a, e0, e1);
+    case 32: return ksc::launch_spec_row_f64_32(odd, W, mode, grid, lds, s, a, e0, e1);
+    case 64: return ksc::launch_spec_row_f64_64(odd, W, mode, grid, lds, s, a, e0, e1);
     default: return hipErrorInvalidValue;
   }
 }
@@ -684,14 +688,17 @@ ksc_status launch_spectral(ksc_problem* p, int mode, const void* in, void* out,
   ga.scale = scale;
   ga.active = active;
   ga.curves = p->d_spec;
+  ga.part = p->d_kpart;
+  ga.part_stride = (long long)(p->state_bytes() / p->esize());
   // 1. Y = D_t U
   for (int l = 0; l < nl; ++l) {
     const auto& G = p->spec_launches[l];
     ksc::SpecArgs<T> a = ga;
+    a.kparts = G.kparts;
     a.b = static_cast<const T*>(in);
     a.out = static_cast<T*>(p->d_Y);
-    hipError_t e = spec_gemm(G.nx, ksc::EPI_Y, p->d_sgroups + G.gfirst, G.ngroups, G.n_blocks, s, a,
-                             l == 0 ? e_first : nullptr, nullptr);
+    hipError_t e = spec_gemm(G.nx, p->odd(), ksc::EPI_Y, p->d_sgroups + G.gfirst, G.ngroups,
+                             G.n_blocks, s, a, l == 0 ? e_first : nullptr, nullptr);
     if (e != hipSuccess) return fail(KSC_ERR_HIP, std::string("spectral product: ") + hipGetErrorString(e));
   }
   // 2. rows: residual, cost partials, row-local adjoint part
@@ -712,8 +719,8 @@ ksc_status launch_spectral(ksc_problem* p, int mode, const void* in, void* out,
     int grid = t1 - t0;
     if (p->policy == KSC_LAUNCH_PERSISTENT) grid = std::min(grid, p->n_cu * (W == 1 ? 4 : 2));
     const bool last = (mode == ksc::MODE_J) && t1 == nt;
-    hipError_t e = spec_row(nx, W, mode == ksc::MODE_J ? ksc::MODE_J : ksc::MODE_GRAD, grid,
-                            lds_for(p, W, nx), s, rg, nullptr, last ? e_last : nullptr);
+    hipError_t e = spec_row(nx, p->odd(), W, mode == ksc::MODE_J ? ksc::MODE_J : ksc::MODE_GRAD,
+                            grid, lds_for(p, W, nx), s, rg, nullptr, last ? e_last : nullptr);
     if (e != hipSuccess) return fail(KSC_ERR_HIP, std::string("spectral rows: ") + hipGetErrorString(e));
     t0 = t1;
   }
@@ -722,11 +729,12 @@ ksc_status launch_spectral(ksc_problem* p, int mode, const void* in, void* out,
   for (int l = 0; l < nl; ++l) {
     const auto& G = p->spec_launches[l];
     ksc::SpecArgs<T> a = ga;
+    a.kparts = G.kparts;
     a.b = static_cast<const T*>(p->d_WR);
     a.p = static_cast<const T*>(p->d_P);
     a.u = static_cast<const T*>(in);
     a.out = static_cast<T*>(out);
-    hipError_t e = spec_gemm(G.nx, mode == ksc::MODE_GRAD ? ksc::EPI_GRAD : ksc::EPI_STEP,
+    hipError_t e = spec_gemm(G.nx, p->odd(), mode == ksc::MODE_GRAD ? ksc::EPI_GRAD : ksc::EPI_STEP,
                              p->d_sgroups + G.gfirst, G.ngroups, G.n_blocks, s, a, nullptr,
                              l == nl - 1 ? e_last : nullptr);
     if (e != hipSuccess) return fail(KSC_ERR_HIP, std::string("spectral product: ") + hipGetErrorString(e));
@@ -817,14 +825,27 @@ ksc_status setup_spectral(ksc_problem* p) {
   p->spec_launches.clear();
   for (const auto& G : p->spec_groups) {
     if (p->spec_launches.empty() || p->spec_launches.back().nx != G.nx)
-      p->spec_launches.push_back({G.nx, int(gd.size()), 0, 0});
+      p->spec_launches.push_back({G.nx, int(gd.size()), 0, 0, 1, 0});
     auto& Lh = p->spec_launches.back();
-    const int cb = ksc::spec_curves_per_block(G.nx);
+    const int cb = ksc::spec_curves_per_block(G.nx, p->odd());
     const int rb = (G.n_s + ksc::kSpecRowsPerBlock - 1) / ksc::kSpecRowsPerBlock;
     gd.push_back({G.first, G.count, rb, Lh.n_blocks});
     Lh.ngroups++;
     Lh.n_blocks += rb * ((G.count + cb - 1) / cb);
+    Lh.nk_max = std::max(Lh.nk_max, (G.n_s + 31) / 32);
   }
+  // A launch of fewer than 512 workgroups splits its k range into up to 8
+  // parts (at least two k steps of 32 each for the largest n_s): the partial
+  // products go to a work array and a second kernel adds them in part order.
+  int kmax = 1;
+  for (auto& Lh : p->spec_launches) {
+    Lh.kparts = 1;
+    if (Lh.n_blocks < 512)
+      Lh.kparts = std::max(1, std::min({8, (512 + Lh.n_blocks - 1) / Lh.n_blocks, Lh.nk_max / 2}));
+    kmax = std::max(kmax, Lh.kparts);
+  }
+  if (kmax > 1)
+    KSC_HIP(hipMalloc(&p->d_kpart, size_t(kmax) * (p->state_bytes() / p->esize()) * sizeof(double)));
   KSC_HIP(hipMalloc(&p->d_sgroups, gd.size() * sizeof(ksc::SpecGroupDev)));
   KSC_HIP(hipMemcpy(p->d_sgroups, gd.data(), gd.size() * sizeof(ksc::SpecGroupDev),
                     hipMemcpyHostToDevice));
@@ -953,8 +974,6 @@ ksc_status ksc_create_opts(const ksc_curve_desc* descs, int32_t n_curves, const 
   if (ds != KSC_DS_STENCIL && ds != KSC_DS_SPECTRAL)
     return fail(KSC_ERR_ARG, "ksc_create: bad d/ds option");
   if (opts->reserved != 0) return fail(KSC_ERR_ARG, "ksc_create: reserved option must be 0");
-  if (ds == KSC_DS_SPECTRAL && space != KSC_SPACE_FULL)
-    return fail(KSC_ERR_UNSUPPORTED, "ksc_create: the spectral d/ds is built for the full space");
   for (int c = 0; c < n_curves; ++c) {
     const ksc_curve_desc& d = descs[c];
     if (!nx_supported(d.n_x))
@@ -1112,7 +1131,7 @@ ksc_status ksc_destroy(ksc_problem* p) {
   void* bufs[] = {p->d_bounds, p->d_cd,  p->d_tiles, p->d_cs,    p->d_wlT,    p->d_wlD,
                   p->d_A,   p->d_pre,   p->d_sqrtL, p->d_part,   p->d_prevJ2,
                   p->d_flags, p->d_J2,  p->d_edge,  p->d_dpool,  p->d_spec,  p->d_Y,
-                  p->d_WR,  p->d_P,   p->d_sgroups};
+                  p->d_WR,  p->d_P,   p->d_sgroups, p->d_kpart};
   for (void* b : bufs)
     if (b) hipFree(b);
   delete p;

@@ -22,6 +22,7 @@
 // stays near 1e-6 of the gradient.
 #pragma once
 
+#include "ksc_sym.hpp"
 #include "ksc_tile.hpp"
 
 namespace ksc {
@@ -47,6 +48,9 @@ struct SpecArgs {
   const T* __restrict__ pre;            // per mode: -dtau / (1 + dtau A^2)
   const double* __restrict__ scale;     // per curve gradient scale, nullable
   const unsigned char* __restrict__ active;  // per curve, nullable (STEP)
+  double* __restrict__ part;            // split k: partial products, [kparts][state scalars]
+  long long part_stride;                // scalars per partial (the state's scalar count)
+  int kparts;                           // parts of the k range (1: no split)
 };
 
 enum SpecEpi : int { EPI_Y = 0, EPI_GRAD = 1, EPI_STEP = 2 };
@@ -194,6 +198,132 @@ __device__ __forceinline__ void spec_row_body(const SpecRowArgs<T>& sa, const Cu
   }
 }
 
+// The same in the inversion-symmetric subspace (rows of K reals b_k,
+// u_hat_k = i b_k; transforms as in ksc_odd.hpp): rho_k = -y_k + A_k b_k
+// - (q_k / (2N)) (2 C_k) with y = D_t b, the row-local adjoint part
+// P = Im Q_hat + A rho, and WR = 2 w L rho.  The pointers of sa are read as
+// real arrays.
+template <int NX, typename T, int W, int MODE>
+__device__ __forceinline__ void spec_row_body_odd(const SpecRowArgs<T>& sa, const CurveDev& cd,
+                                                  int c, int j0, int tile, T* buf) {
+  const KernelArgs<T>& a = sa.a;
+  constexpr int K = (NX - 1) / 3;
+  constexpr int M2 = NX / 2;
+  constexpr int ROWS = 64 * W;
+  constexpr int E = 16 / int(sizeof(T));
+  constexpr int NB = ROWS * K + 2 * E;
+  const int t = threadIdx.x;
+  const int n_s = cd.n_s;
+  const int jr = j0 + t;
+  const bool interior = (jr >= 1) && (jr <= n_s - 2);
+  const long long base = cd.off + (long long)j0 * K;
+  const long long G_hi = cd.off + (long long)min(n_s, j0 + ROWS) * K;
+  const int sh = int(base % E);
+  T* __restrict__ bu = buf;
+  T* __restrict__ by = buf + NB;
+  __syncthreads();
+  stage_block<T, ROWS, ROWS * K + E>(bu, reinterpret_cast<const T*>(a.in), base, sh, ROWS * K + sh,
+                                     base, G_hi);
+  stage_block<T, ROWS, ROWS * K + E>(by, reinterpret_cast<const T*>(sa.y), base, sh, ROWS * K + sh,
+                                     base, G_hi);
+  __syncthreads();
+  const T* __restrict__ brow = bu + sh + t * K;
+  const T* __restrict__ yrow = by + sh + t * K;
+  const T q1s = T(cd.q1 * cd.q1);
+  const T qN1 = T(cd.q1 / (2.0 * NX));
+  constexpr T iN = T(1.0 / NX);
+
+  T u[M2];
+  {
+    T f[M2];
+    sfor<M2>([&](auto Kk) {
+      constexpr int k = Kk;
+      if constexpr (k >= 1 && k <= K)
+        f[k] = -brow[k - 1];
+      else
+        f[k] = T(0);
+    });
+    dst1_x2<M2, M2, T>(f, u);
+  }
+  T C2[K + 1];
+  {
+    T g[M2 + 1];
+    sfor<M2>([&](auto Nn) {
+      constexpr int n = Nn;
+      g[n] = u[n] * u[n];
+    });
+    g[M2] = T(0);
+    dct1_x2<M2, K + 1, T>(g, C2);
+  }
+  T R[K];
+  T rowR = T(0), rowD = T(0);
+  sfor<K>([&](auto Ee) {
+    constexpr int e = Ee;
+    constexpr int k = e + 1;
+    const T yk = yrow[e];
+    const T qn = T(k) * qN1;
+    const T q2 = T(k * k) * q1s;
+    const T Ak = fmaT(-q2, q2, q2);
+    const T rho = fmaT(Ak, brow[e], fmaT(-qn, C2[k], -yk));
+    rowR = fmaT(rho, rho, rowR);
+    rowD = fmaT(yk, yk, rowD);
+    R[e] = interior ? rho : T(0);
+  });
+  double pj = 0.0, pn = 0.0, pd = 0.0;
+  if (interior) {
+    const double rR = 2.0 * double(rowR);
+    const double wl = a.wlD[cd.row_off + jr];
+    pj = wl * rR;
+    if constexpr (MODE == MODE_J) {
+      const double rD = 2.0 * double(rowD);
+      pn = wl * sqrt(rR * rD);
+      pd = wl * sqrt(rD);
+    }
+  }
+  store_wave_partials<W, (MODE == MODE_J) ? 3 : 1>(pj, pn, pd, tile_partials(a, cd, c, tile, W));
+  if constexpr (MODE != MODE_J) {
+    T G2[K + 1];  // 2 F_k of u r_x = -N Im Q_hat_k
+    {
+      T rx[M2];
+      {
+        const T q1 = T(cd.q1);
+        T g[M2 + 1];
+        sfor<M2 + 1>([&](auto Kk) {
+          constexpr int k = Kk;
+          if constexpr (k >= 1 && k <= K)
+            g[k] = -(T(k) * q1) * R[k - 1];
+          else
+            g[k] = T(0);
+        });
+        dct1_x2<M2, M2, T>(g, rx);
+      }
+      T w[M2];
+      sfor<M2>([&](auto Nn) {
+        constexpr int n = Nn;
+        w[n] = u[n] * rx[n];
+      });
+      dst1_x2<M2, K + 1, T>(w, G2);
+    }
+    const T f0 = interior ? a.wlT[cd.row_off + jr] : T(0);  // 2 w L
+    __syncthreads();
+    T* __restrict__ ow = bu + sh + t * K;
+    T* __restrict__ op = by + sh + t * K;
+    sfor<K>([&](auto Ee) {
+      constexpr int e = Ee;
+      constexpr int k = e + 1;
+      const T q2 = T(k * k) * q1s;
+      const T Ak = fmaT(-q2, q2, q2);
+      ow[e] = f0 * R[e];
+      op[e] = interior ? fmaT(Ak, R[e], -iN * G2[k]) : T(0);
+    });
+    __syncthreads();
+    flush_block<T, ROWS, ROWS * K + E, false>(reinterpret_cast<T*>(sa.wr), nullptr, bu, base, sh,
+                                              ROWS * K + sh, base, G_hi);
+    flush_block<T, ROWS, ROWS * K + E, false>(reinterpret_cast<T*>(sa.pl), nullptr, by, base, sh,
+                                              ROWS * K + sh, base, G_hi);
+  }
+}
+
 // ---------------------------------------------------------------------------
 // C = op(D~) B / S per curve on FP64 matrix cores: D~ is n_s x n_s (op = transpose
 // for TRANS), B the curve's state viewed as an n_s x NC real matrix (NC =
@@ -236,6 +366,53 @@ template <int NCP>
 constexpr int spec_cb() {
   return (NCP / 16) >= 3 ? 1 : (NCP / 16) == 2 ? 2 : 3;
 }
+// Columns of a curve's state viewed as a real matrix, and the scalar offset
+// of its row 0: full space 2(K+1) (col = 2k + re/im), odd subspace K
+// (col = k - 1, the reals b_k).
+template <bool ODD>
+__device__ __forceinline__ int spec_cols(const SpecDev& cd) {
+  return ODD ? cd.km - 1 : 2 * cd.km;
+}
+template <bool ODD>
+__device__ __forceinline__ long long spec_base(const SpecDev& cd) {
+  return ODD ? cd.off : 2 * cd.off;
+}
+
+// The output of element (row, col) of curve cd's product C = op(D~) B (before
+// the 1/S): the product rounded to the state dtype (EPI_Y) or the gradient /
+// stepped state formed from it as in the row kernels.  In the odd subspace
+// every kept mode k = col + 1 has c_k = 2.
+template <typename T, int EPI, bool ODD>
+__device__ __forceinline__ void spec_store(const SpecArgs<T>& sa, const SpecDev& cd, int row,
+                                           int col, double acc) {
+  const int NC = spec_cols<ODD>(cd);
+  const int n_s = cd.n_s;
+  const int k = ODD ? col + 1 : col >> 1;
+  const bool im0 = !ODD && (col == 1);
+  const long long idx = spec_base<ODD>(cd) + (long long)row * NC + col;
+  const T z = T(acc * cd.inv_S);
+  const bool interior = row >= 1 && row <= n_s - 2;
+  if constexpr (EPI == EPI_Y) {
+    sa.out[idx] = z;
+  } else if constexpr (EPI == EPI_GRAD) {
+    const T sc = (sa.scale != nullptr) ? T(sa.scale[cd.c]) : T(1);
+    const T pv = sa.p[idx];
+    const T f = sa.wlT[cd.row_off + row];
+    const T ck = (k == 0) ? T(1) : T(2);
+    sa.out[idx] = (interior && !im0) ? (ck * sc) * fmaT(f, pv, -z) : T(0);
+  } else {
+    const bool act = (sa.active == nullptr) || sa.active[cd.c] != 0;
+    const T uv = sa.u[idx];
+    T o = uv;
+    if (interior && act) {
+      const T pv = sa.p[idx];
+      const T f = sa.wlT[cd.row_off + row];
+      o = fmaT(sa.pre[cd.mode_off + k], pv - z / f, uv);
+    }
+    sa.out[idx] = im0 ? T(0) : o;
+  }
+}
+
 // LDS of one product workgroup (doubles): the A and B tiles with padded rows.
 template <int NCP>
 constexpr int spec_gemm_lds() {
@@ -245,9 +422,12 @@ constexpr int spec_gemm_lds() {
 
 // Rows row0 .. row0+63 of C for the curves cbase .. cbase+CB-1 of a group of
 // `count` curves that share n_s (and hence D~).
-template <typename T, int NCP, bool TRANS, int EPI>
+// Part kp of sa.kparts of the k range: with one part the epilogue writes the
+// output; with several, the raw partial products go to sa.part and
+// spec_reduce forms the output.
+template <typename T, int NCP, bool TRANS, int EPI, bool ODD>
 __device__ __forceinline__ void spec_gemm_body(const SpecArgs<T>& sa, int count, int cbase,
-                                               int row0, double* lds) {
+                                               int row0, int kp, double* lds) {
   using mma = mfma_acc<double>;
   using acc_t = typename mma::v;
   constexpr int BM = 64, BK = 32;
@@ -266,12 +446,12 @@ __device__ __forceinline__ void spec_gemm_body(const SpecArgs<T>& sa, int count,
   const int lane = t & 63, w = t >> 6;
   const SpecDev c0 = sa.curves[cbase];
   const int n_s = c0.n_s;
-  const int NC = 2 * c0.km;
+  const int NC = spec_cols<ODD>(c0);
   const double* __restrict__ D = sa.dpool + c0.dmat;
   long long boff[CB];  // scalar offset of each curve's state block, -1 past the group
 #pragma unroll
   for (int cb = 0; cb < CB; ++cb)
-    boff[cb] = (cbase + cb < count) ? 2 * sa.curves[cbase + cb].off : -1;
+    boff[cb] = (cbase + cb < count) ? spec_base<ODD>(sa.curves[cbase + cb]) : -1;
   double* As = lds;               // [BK][SA]
   double* Bs = lds + BK * SA;     // [BK][SB]
 
@@ -325,15 +505,19 @@ __device__ __forceinline__ void spec_gemm_body(const SpecArgs<T>& sa, int count,
     }
   };
 
+  // this part's k range, whole k steps
+  const int nk = (n_s + BK - 1) / BK;
+  const int per = (nk + sa.kparts - 1) / sa.kparts;
+  const int k_lo = kp * per * BK, k_hi = min(n_s, (kp + 1) * per * BK);
   acc_t acc[NJ];
 #pragma unroll
   for (int j = 0; j < NJ; ++j) acc[j] = acc_t{0.0, 0.0, 0.0, 0.0};
-  load(0);
-  for (int k0 = 0; k0 < n_s; k0 += BK) {
+  if (k_lo < k_hi) load(k_lo);
+  for (int k0 = k_lo; k0 < k_hi; k0 += BK) {
     __syncthreads();  // the previous step's reads of the tiles are done
     store();
     __syncthreads();
-    if (k0 + BK < n_s) load(k0 + BK);
+    if (k0 + BK < k_hi) load(k0 + BK);
 #pragma unroll
     for (int s = 0; s < BK / 4; ++s) {
       const int kk = 4 * s + (lane >> 4);
@@ -346,50 +530,51 @@ __device__ __forceinline__ void spec_gemm_body(const SpecArgs<T>& sa, int count,
     }
   }
 
-  // epilogue: element (row, col) of curve cb's C, col = 2k + (0: re, 1: im);
-  // the product is rounded to the state dtype, the rest as in the row kernels
+  // epilogue: element (row, col) of curve cb's C
 #pragma unroll
   for (int cb = 0; cb < CB; ++cb) {
     if (cbase + cb >= count) break;
     const SpecDev cd = sa.curves[cbase + cb];
-    const int c = cd.c;
-    const double inv_S = cd.inv_S;
-    const bool act = (sa.active == nullptr) || sa.active[c] != 0;
-    const T sc = (EPI == EPI_GRAD && sa.scale != nullptr) ? T(sa.scale[c]) : T(1);
-    T* __restrict__ O = sa.out + 2 * cd.off;
 #pragma unroll
     for (int jt = 0; jt < NT; ++jt) {
       const int j = cb * NT + jt;
       const int col = 16 * jt + (lane & 15);
-      const int k = col >> 1;
-      const bool im0 = (col == 1);
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int row = row0 + 16 * w + mma::row(lane, r);
         if (row >= n_s || col >= NC) continue;
-        const long long idx = (long long)row * NC + col;
-        const T z = T(acc[j][r] * inv_S);
-        const bool interior = row >= 1 && row <= n_s - 2;
-        if constexpr (EPI == EPI_Y) {
-          O[idx] = z;
-        } else if constexpr (EPI == EPI_GRAD) {
-          const T pv = sa.p[2 * cd.off + idx];
-          const T f = sa.wlT[cd.row_off + row];
-          const T ck = (k == 0) ? T(1) : T(2);
-          O[idx] = (interior && !im0) ? (ck * sc) * fmaT(f, pv, -z) : T(0);
-        } else {
-          const T uv = sa.u[2 * cd.off + idx];
-          T o = uv;
-          if (interior && act) {
-            const T pv = sa.p[2 * cd.off + idx];
-            const T f = sa.wlT[cd.row_off + row];
-            o = fmaT(sa.pre[cd.mode_off + k], pv - z / f, uv);
-          }
-          O[idx] = im0 ? T(0) : o;
-        }
+        if (sa.kparts == 1)
+          spec_store<T, EPI, ODD>(sa, cd, row, col, acc[j][r]);
+        else
+          sa.part[kp * sa.part_stride + spec_base<ODD>(cd) + (long long)row * NC + col] = acc[j][r];
       }
     }
   }
+}
+
+// Sum of the kparts (at most 8) partial products of one element in part order
+// (deterministic) and the epilogue.  The elements of a product workgroup's
+// tile (64 rows x CB curves x NC columns) are spread over `chunk` workgroups
+// of 256 threads, one element per thread, so that the partial loads of all
+// elements are in flight together.
+template <typename T, int NCP, int EPI, bool ODD>
+__device__ __forceinline__ void spec_reduce_body(const SpecArgs<T>& sa, int count, int cbase,
+                                                 int row0, int chunk) {
+  const SpecDev c0 = sa.curves[cbase];
+  const int NC = spec_cols<ODD>(c0);
+  const int e = chunk * 256 + threadIdx.x;
+  const int cb = e / (64 * NC), rem = e % (64 * NC);
+  const int row = row0 + rem / NC, col = rem % NC;
+  if (cb >= spec_cb<NCP>() || cbase + cb >= count || row >= c0.n_s) return;
+  const SpecDev cd = sa.curves[cbase + cb];
+  const long long idx = spec_base<ODD>(cd) + (long long)row * NC + col;
+  double v[8];
+#pragma unroll
+  for (int kp = 0; kp < 8; ++kp) v[kp] = (kp < sa.kparts) ? sa.part[kp * sa.part_stride + idx] : 0.0;
+  double acc = 0.0;
+#pragma unroll
+  for (int kp = 0; kp < 8; ++kp) acc += v[kp];
+  spec_store<T, EPI, ODD>(sa, cd, row, col, acc);
 }
 
 }  // namespace ksc

@@ -231,6 +231,9 @@ def main(argv=None):
     ap.add_argument("--ds", default=None, choices=["stencil", "spectral"],
                     help="d/ds (default: spectral with --connection, else stencil)")
     ap.add_argument("--S", type=float, default=55.0, help="rational map scale (--connection)")
+    ap.add_argument("--space", default=None, choices=["full", "odd"],
+                    help="state space (default: odd, the inversion-symmetric subspace the paper "
+                         "searches, with --connection / --table2; else full)")
     ap.add_argument("--dtype", default=None, choices=["f32", "f64"],
                     help="start precision (default: f64 with --connection, else f32)")
     ap.add_argument("--jarc-target", type=float, default=None,
@@ -254,6 +257,7 @@ def main(argv=None):
         made = [ksinputs.l22_connection_curve(a, b, n_s, args.S) for a, b in pairs]
         specs, Us = [m[0] for m in made], [m[1] for m in made]
         labels = [p for p in args.connection.split(",")]
+    space = args.space or ("odd" if args.connection else "full")
     if args.connection:
         ds = args.ds or "spectral"
         dt = torch.float64 if (args.dtype or "f64") == "f64" else torch.float32
@@ -268,7 +272,11 @@ def main(argv=None):
         ds = args.ds or "stencil"
         dt = torch.float64 if args.dtype == "f64" else torch.float32
     prob = Problem([CurveDesc(s.n_s, s.n_x, s.L, s.map, s.scale, s.s0) for s in specs],
-                   dtype=dt, ds=ds)
+                   dtype=dt, ds=ds, space=space)
+    if space == "odd":
+        if any(np.abs(U.real).max() > 0 for U in Us):
+            raise ValueError("the odd subspace needs inversion-symmetric curves (u_hat_k = i b_k)")
+        Us = [np.ascontiguousarray(U[:, 1:].imag) for U in Us]
     prob.tune(None)
     X = prob.new_state()
     for c, U in enumerate(Us):
@@ -276,7 +284,8 @@ def main(argv=None):
     b = GpuBackend(prob, X)
     t0 = time.time()
     J0 = np.sqrt(b.J2())
-    print(f"start: {len(specs)} curves ({ds} d/ds), J max {J0.max():.3e} min {J0.min():.3e}"
+    print(f"start: {len(specs)} curves ({ds} d/ds, {space} space), J max {J0.max():.3e} "
+          f"min {J0.min():.3e}"
           + (f", J_arc {np.array2string(b.J_arc(), precision=3)}" if args.jarc_target else ""),
           flush=True)
 
@@ -317,7 +326,8 @@ def main(argv=None):
         with open(args.history, "w") as fh:
             json.dump({"curves": [f"{sp.n_x}x{sp.n_s} L={sp.L} S={sp.scale}" for sp in specs],
                        "labels": labels,
-                       "connection": args.connection, "ds": ds, "dtau0": args.dtau,
+                       "connection": args.connection, "ds": ds, "space": space,
+                       "dtau0": args.dtau,
                        "records": [{"step": st, "tau": st * args.dtau, "J": list(map(float, j)),
                                     "J_arc": arc.get(st)} for st, j in log.J_history],
                        "events": log.events}, fh)

@@ -102,8 +102,8 @@ def test_create2_validates_the_state_space():
 
 
 def test_create_opts_validates_the_spectral_ds():
-    """ksc_create_opts: the spectral d/ds needs the rational map, the full
-    space, one row per lane (n_x <= 128 in FP32, <= 64 in FP64) and
+    """ksc_create_opts: the spectral d/ds needs the rational map, one row per
+    lane (n_x <= 128 in FP32, <= 64 in FP64, in either space) and
     n_s <= 16384; unknown options and a non-zero reserved field are argument
     errors; all reported before any HIP call."""
     from paper_2301_11704_amd import _lib
@@ -121,7 +121,7 @@ def test_create_opts_validates_the_spectral_ds():
     assert create(ds=2) == -1
     assert create(reserved=1) == -1
     assert create(map_=1) == -1 and b"rational" in L.ksc_last_error()
-    assert create(space=1) == -3
+    assert create(space=1, n_x=256) == -3
     assert create(n_x=256) == -3
     assert create(dtype=1, n_x=128) == -3 and b"64 in FP64" in L.ksc_last_error()
     assert create(n_s=16385) == -3

@@ -234,3 +234,68 @@ def test_spectral_descent_from_E1_to_E2_matches_oracle():
     trc = tr.cpu().numpy()[:, 0]
     for g in range(3):
         assert abs(trc[g] - Jr[20 * g + 19]) <= 60 * TOL[np.float64] * Jr[20 * g + 19]
+
+
+def _embed(B):
+    U = np.zeros((B.shape[0], B.shape[1] + 1), dtype=np.complex128)
+    U[:, 1:] = 1j * B
+    return U
+
+
+@pytest.mark.parametrize("dtype", [np.float64, np.float32])
+@pytest.mark.parametrize("n_s,n_x", [(3, 16), (17, 8), (130, 32), (300, 64), (552, 64), (200, 128)])
+def test_spectral_odd_parity(dtype, n_s, n_x):
+    """The spectral d/ds in the inversion-symmetric subspace (rows of K reals)
+    against the oracle's restriction to it."""
+    import paper_2301_11704_amd as ksc
+    print(f"spectral odd parity n_s={n_s} n_x={n_x} dtype={dtype.__name__}", flush=True)
+    if dtype == np.float64 and n_x > 64:
+        pytest.skip("the spectral d/ds in FP64 supports n_x <= 64")
+    spec = _spec(n_s, n_x, 22.0 if n_x <= 64 else 39.0, (116, n_s, n_x))
+    descs = [ksc.CurveDesc(spec.n_s, spec.n_x, spec.L, spec.map, spec.scale, spec.s0)]
+    prob = ksc.Problem(descs, dtype=_tdt(dtype), ds="spectral", space="odd")
+    U = _state(spec, dtype)
+    B = np.ascontiguousarray(U[:, 1:].imag)
+    X = prob.new_state()
+    prob.upload(X, 0, B)
+    c = _curve(spec)
+    J2, Jarc = prob.eval_J(X, arc=True)
+    G, J2g = prob.eval_grad(X)
+    Y = torch.empty_like(X)
+    prob.step(X, Y, 1e-4)
+    torch.cuda.synchronize()
+    tol = TOL[dtype]
+    ref = oracle.J2_odd(c, B)
+    assert abs(J2.item() - ref) <= tol * ref and abs(J2g.item() - ref) <= tol * ref
+    Ja = oracle.J_arc_odd(c, B)
+    assert abs(Jarc.item() - Ja) <= 10 * tol * Ja
+    Gg, Gr = _embed(prob.download(G, 0)), _embed(oracle.grad_odd(c, B))
+    tg = _grad_tol(c, _embed(B), dtype)
+    e_pre = precond_rel_err(c, Gg, Gr)
+    e_dir = directional_rel_err(c, Gg, Gr, [(117, j) for j in range(8)])
+    print(f"gradient errors: preconditioned {e_pre:.2e}, directional {e_dir:.2e} (gate {tg:.1e})",
+          flush=True)
+    assert e_pre <= tg and e_dir <= tg
+    got, want = prob.download(Y, 0), oracle.step_odd(c, B, 1e-4)
+    assert np.array_equal(got[0], B[0]) and np.array_equal(got[-1], B[-1])
+    assert np.linalg.norm(got - want) / np.linalg.norm(want) <= tol
+
+
+def test_spectral_odd_descent_matches_full_space():
+    """E1 -> E2 for 60 steps in the odd subspace and in the full space: the
+    same trajectory (the full-space run's imaginary parts) to rounding."""
+    import paper_2301_11704_amd as ksc
+    spec, U = ksinputs.l22_connection_curve("E1", "E2")
+    d = [ksc.CurveDesc(spec.n_s, spec.n_x, spec.L, spec.map, spec.scale, spec.s0)]
+    pf = ksc.Problem(d, dtype=torch.float64, ds="spectral")
+    po = ksc.Problem(d, dtype=torch.float64, ds="spectral", space="odd")
+    Xf, Xo = pf.new_state(), po.new_state()
+    pf.upload(Xf, 0, U)
+    po.upload(Xo, 0, np.ascontiguousarray(U[:, 1:].imag))
+    tf = pf.descend(Xf, 60, 0.01, every=20)
+    to = po.descend(Xo, 60, 0.01, every=20)
+    torch.cuda.synchronize()
+    uf, bo = pf.download(Xf, 0), po.download(Xo, 0)
+    assert np.abs(uf.real).max() <= 1e-14 * np.abs(uf).max()
+    assert np.linalg.norm(bo - uf[:, 1:].imag) <= 60 * TOL[np.float64] * np.linalg.norm(bo)
+    assert np.allclose(to.cpu().numpy(), tf.cpu().numpy(), rtol=60 * TOL[np.float64], atol=0)
