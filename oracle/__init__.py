@@ -34,6 +34,9 @@ from .ks import (  # noqa: F401
     J_arc_odd,
     grad_odd,
     step_odd,
+    implicit_s_operator,
+    step_implicit_s,
+    step_implicit_s_odd,
     from_physical_curve,
     to_physical_curve,
 )

@@ -426,3 +426,75 @@ def grad_odd(c: Curve, B: np.ndarray) -> np.ndarray:
 def step_odd(c: Curve, B: np.ndarray, dtau: float) -> np.ndarray:
     """One semi-implicit step of eq. KSE_G, which stays in the subspace."""
     return full_to_odd(step(c, odd_to_full(B), dtau))
+
+
+# ----------------------------------------------------------------------------
+# A descent step with the s-part of the linear operator implicit as well (an
+# extension of the semi-implicit scheme of Sec. V.C.3; not in the paper).
+# ----------------------------------------------------------------------------
+
+def implicit_s_operator(c: Curve, k: int) -> np.ndarray:
+    """The part of L^dagger(u; r(u)) that is linear in the interior rows of
+    mode k, as an (n_s - 2) x (n_s - 2) matrix B_k acting on those rows:
+
+        B_k = A_k^2 I - D m D,
+
+    D the central difference of ``_ds`` on the interior rows (reading the
+    neighbour rows) and m the mask that zeroes the end rows of the residual
+    before the second d/ds.  The residual's linear part is A u - u_s and the
+    adjoint's is r_s + A r, so the cross terms A u_s cancel and what remains
+    is A^2 u - (m u_s)_s; couplings of an interior row to the fixed end rows
+    are constants, not part of B_k.  Stencil d/ds only.
+
+    Parity: pinned by the Jacobian of ``adjoint`` at u = 0 (central
+    differences, exact for the polynomial map up to rounding).
+    """
+    if c.ds != "stencil":
+        raise ValueError("the banded operator is the central-difference one")
+    n = c.n_s
+    ni = n - 2
+    beta = np.zeros(n)
+    beta[1:-1] = c.g[1:-1] / (2.0 * c.dsigma)   # d/ds at row j: beta_j (q_{j+1} - q_{j-1})
+    # first derivative on the interior rows, as a map from all rows
+    Dfull = np.zeros((n, n))
+    for j in range(1, n - 1):
+        Dfull[j, j + 1] = beta[j]
+        Dfull[j, j - 1] = -beta[j]
+    DmD = Dfull @ Dfull          # rows and columns of the end rows of the inner D are zero
+    B = c.A[k] ** 2 * np.eye(ni) - DmD[1:-1, 1:-1]
+    return B
+
+
+def step_implicit_s(c: Curve, U: np.ndarray, dtau: float) -> np.ndarray:
+    """One linearly implicit Euler step of du/dtau = -L^dagger(u; r) in which
+    the whole linear part B_k of ``implicit_s_operator`` is implicit (the
+    paper's step makes only A_k^2 implicit):
+
+        (I + dtau B_k) delta_k = -dtau L^dagger_k,   u_hat <- u_hat + delta
+
+    on the interior rows of every mode k; end rows unchanged, Im of mode 0
+    zero.  B_k is self-adjoint and positive semi-definite in the weighted
+    inner product, so -delta is a descent direction for J^2 at any dtau > 0,
+    and fixed points are those of the paper's flow.
+
+    Parity: pinned through ``implicit_s_operator``; the step itself by its
+    first-order agreement with ``step`` as dtau -> 0 and by monotone decrease
+    of J^2.
+    """
+    U = _clean(c, U)
+    Ad = adjoint(c, U)
+    out = U.copy()
+    ni = c.n_s - 2
+    if ni <= 0:
+        return out
+    for k in range(c.K + 1):
+        M = np.eye(ni) + dtau * implicit_s_operator(c, k)
+        out[1:-1, k] = U[1:-1, k] + np.linalg.solve(M, -dtau * Ad[1:-1, k])
+    out[:, 0] = out[:, 0].real
+    return out
+
+
+def step_implicit_s_odd(c: Curve, B: np.ndarray, dtau: float) -> np.ndarray:
+    """``step_implicit_s`` of the inversion-symmetric curve b (B_k is real and
+    acts per mode, so the step stays in the subspace)."""
+    return full_to_odd(step_implicit_s(c, odd_to_full(B), dtau))
