@@ -73,7 +73,7 @@ KERNEL_SOURCES = {
 # workloads, so that every run (and every profiler run) uses the same shape.
 TUNE_CACHE = os.path.join(ROOT, "paper_2301_11704_amd", "tuning_gfx950.json")
 STREAM_REPLICAS = {"c4": 48, "c2": 191, "c3": 20, "c1": 0}
-DTAU = {"c4": 5e-4, "c2": 1e-4, "c3": 1e-3, "c1": 1e-3}
+DTAU = {"c4": 5e-4, "c2": 1e-4, "c3": 1e-3, "c1": 1e-3, "p22": 0.01}
 
 
 def kernel_source_hash(space: str = "full") -> str:
@@ -311,6 +311,35 @@ def odd_leg(ksc, torch, descs, Us, tdt, esz, specs, args, stream, full_kernel_ms
     return res
 
 
+def implicit_s_leg(ksc, torch, descs, Us, tdt, esz, args, stream, ms_paper):
+    """The implicit-in-s descent step (the whole linear part implicit, banded
+    solves along s) on the same curves: ms per step in captured-graph descent
+    against the paper's step, and the solve's share (the step minus the J +
+    gradient evaluation it starts with)."""
+    pi = ksc.Problem(descs, dtype=tdt, space=args.space)
+    pi.set_scheme("implicit_s")
+    Xi = pi.new_state()
+    for c, U in enumerate(odd_states(Us) if args.space == "odd" else Us):
+        pi.upload(Xi, c, U)
+    Gi = torch.empty_like(Xi)
+    Si = torch.empty_like(Xi)
+    pi.tune(None if args.retune else args.tune_cache)
+    dtau = DTAU[args.workload]
+    pi.descend(Xi, 200, dtau, every=100, scratch=Si)
+    nd = 100 * max(2, args.steps // 50)
+    ms_i = _time(torch, lambda: pi.descend(Xi, nd, dtau, every=100, scratch=Si), 1, stream) / nd
+    ms_g = _time(torch, lambda: pi.eval_grad(Xi, Gi), args.steps, stream)
+    solve_ms = max(ms_i - ms_g, 0.0)
+    state_b = Xi.numel() * esz
+    res = {"ms_per_step": ms_i, "ms_per_step_paper_scheme": ms_paper,
+           "cost_ratio_vs_paper_step": ms_i / ms_paper, "eval_grad_ms": ms_g,
+           "solve_ms_est": solve_ms,
+           # the solve reads the state and the gradient and writes the next state
+           "solve_alg_GBs_est": 3 * state_b / (solve_ms * 1e-3) / 1e9 if solve_ms > 0 else None}
+    del Xi, Gi, Si, pi
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -469,6 +498,9 @@ def main():
                            "GBs_vs_method_minimum": alg_bytes / (ms_ag * 1e-3) / 1e9,
                            "GBs_vs_recompute_design": 1.5 * alg_bytes / (ms_ag * 1e-3) / 1e9}
         del Xr, Y
+        if args.ds == "stencil":
+            out["implicit_s"] = implicit_s_leg(ksc, torch, descs, Us, tdt, esz, args, stream,
+                                               ms_d / nd)
         if args.ds == "stencil" and args.dtype == "f32":
             out["spectral_ds"] = spectral_leg(ksc, torch, tdt, esz, args, stream)
         if args.space == "full" and args.ds == "stencil" and \

@@ -117,6 +117,12 @@ typedef enum {
   KSC_MAP_FINITE = 1    /* s = scale * sigma; scale is the length T */
 } ksc_map;
 
+/* Descent scheme of ksc_step and ksc_descend (ksc_set_scheme). */
+typedef enum {
+  KSC_SCHEME_PAPER = 0,     /* the paper's semi-implicit step (Sec. V.C.3) */
+  KSC_SCHEME_IMPLICIT_S = 1 /* the whole linear part implicit, including d/ds */
+} ksc_scheme;
+
 /* Per-curve flag bits reported by ksc_query_flags. */
 #define KSC_FLAG_NONFINITE 1u  /* the last J2 of the curve was NaN or Inf */
 #define KSC_FLAG_INCREASED 2u  /* J2 rose between two consecutive descent steps */
@@ -209,6 +215,27 @@ ksc_status ksc_step(ksc_problem* p, const void* state_in, void* state_out, doubl
  * every must be >= 1; n_steps >= 0. */
 ksc_status ksc_descend(ksc_problem* p, void* state, void* scratch, int64_t n_steps, double dtau,
                        double* J2_trace, int32_t every, const uint8_t* active);
+
+/* Select the descent scheme of later ksc_step / ksc_descend calls.
+ * KSC_SCHEME_PAPER (the default) is the step described at the top of this
+ * file.  KSC_SCHEME_IMPLICIT_S (an extension, not in the paper) makes the
+ * whole part of L^dagger(u; r(u)) that is linear in u implicit: on the
+ * interior rows of every mode k it solves
+ *     (I + dtau B_k) delta = -dtau L^dagger_k,  B_k = A_k^2 - D m D,
+ * and writes u_hat + delta, where D is the central difference along s and m
+ * zeroes the end rows of the residual (r = f(u) - u_s and
+ * L^dagger r = r_s + u r_x - r_xx - r_xxxx of Sec. V.A; the cross terms
+ * cancel).  B_k is self-adjoint and positive semi-definite in the weighted
+ * inner product, so the step is a descent direction at any dtau > 0, its
+ * fixed points are those of the paper's flow, and dtau is no longer bounded
+ * by the s-resolution.  D m D couples rows two apart: two tridiagonal systems
+ * per curve and mode, solved on the device in the problem's dtype.  Endpoint
+ * rows, Im of mode 0 and the `active` mask behave as for the paper's step.
+ * Needs KSC_DS_STENCIL (KSC_ERR_UNSUPPORTED for spectral d/ds) and
+ * n_s <= 8194 (KSC_ERR_UNSUPPORTED).  Allocates one state-sized gradient
+ * buffer and a solve table on first use; blocks the host. */
+ksc_status ksc_set_scheme(ksc_problem* p, int32_t scheme);
+ksc_status ksc_get_scheme(const ksc_problem* p, int32_t* scheme);
 
 /* Choose the launch shape (waves per tile, persistent or not) by timing the
  * candidates on scratch buffers; the choice is cached in the JSON file at

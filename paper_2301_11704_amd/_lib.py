@@ -19,6 +19,7 @@ KSC_DS_STENCIL, KSC_DS_SPECTRAL = 0, 1
 KSC_MAP_RATIONAL, KSC_MAP_FINITE = 0, 1
 KSC_FLAG_NONFINITE, KSC_FLAG_INCREASED = 1, 2
 KSC_LAUNCH_AUTO, KSC_LAUNCH_PLAIN, KSC_LAUNCH_PERSISTENT = 0, 1, 2
+KSC_SCHEME_PAPER, KSC_SCHEME_IMPLICIT_S = 0, 1
 
 # Every symbol include/ksc.h declares.
 EXPORTED = (
@@ -26,7 +27,7 @@ EXPORTED = (
     "ksc_phys_numel", "ksc_phys_offset", "ksc_n_modes", "ksc_set_endpoints",
     "ksc_phys_to_spec", "ksc_spec_to_phys", "ksc_eval_J", "ksc_eval_grad", "ksc_step",
     "ksc_descend", "ksc_tune", "ksc_set_launch", "ksc_get_launch", "ksc_query_flags",
-    "ksc_set_timing", "ksc_read_timing", "ksc_last_error",
+    "ksc_set_timing", "ksc_read_timing", "ksc_set_scheme", "ksc_get_scheme", "ksc_last_error",
 )
 
 
@@ -92,6 +93,8 @@ def lib() -> ctypes.CDLL:
         "ksc_tune": (i32, [vp, ctypes.c_char_p]),
         "ksc_set_launch": (i32, [vp, i32, i32]),
         "ksc_get_launch": (i32, [vp, ctypes.POINTER(i32), ctypes.POINTER(i32)]),
+        "ksc_set_scheme": (i32, [vp, i32]),
+        "ksc_get_scheme": (i32, [vp, ctypes.POINTER(i32)]),
         "ksc_query_flags": (i32, [vp, ctypes.POINTER(ctypes.c_uint32)]),
         "ksc_set_timing": (i32, [vp, i32]),
         "ksc_read_timing": (i32, [vp, ctypes.POINTER(dbl), ctypes.POINTER(dbl),

@@ -45,6 +45,7 @@ def units():
             out.append((f"spec_{tname}_{nx}", "ksc_spec.hip", d + [f"-DKSC_NX={nx}"]))
         out.append((f"mixed_{tname}", "ksc_fused.hip", d + ["-DKSC_MIXED"]))
         out.append((f"oddconv_{tname}", "ksc_odd.hip", d + ["-DKSC_ODD_CONV"]))
+    out.append(("simp", "ksc_simp.hip", []))
     return out
 
 

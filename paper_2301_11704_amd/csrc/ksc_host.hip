@@ -17,6 +17,7 @@
 #include "ksc_launch.hpp"
 #include "ksc_launch_odd.hpp"
 #include "ksc_launch_spec.hpp"
+#include "ksc_launch_simp.hpp"
 
 using ksc::cplx;
 using ksc::CurveDev;
@@ -281,6 +282,14 @@ struct ksc_problem {
   void* d_Y = nullptr;
   void* d_WR = nullptr;
   void* d_P = nullptr;
+
+  // descent scheme (ksc_set_scheme); the implicit-in-s step keeps the
+  // gradient in d_G and walks the solve table d_simp
+  int scheme = KSC_SCHEME_PAPER;
+  void* d_G = nullptr;
+  ksc::SimpBlock* d_simp = nullptr;
+  int n_simp = 0;
+  int simp_chunk = 16;
 
   // descent graph cache
   hipStream_t cap_stream = nullptr;
@@ -935,6 +944,83 @@ ksc_status ensure_pre(ksc_problem* p, double dtau, hipStream_t s) {
   return KSC_OK;
 }
 
+// Solve table of the implicit-in-s step: per curve and chain (odd rows, even
+// rows), P chunks (a power of two with P * chunk >= chain rows, at least
+// 256 / CW for CW the mode columns rounded up to a power of two) and the mode
+// columns in groups of 256 / P; chunk = 8 rows per thread when every chain
+// fits 256 * 8 rows, else 16.
+ksc_status build_simp(ksc_problem* p) {
+  std::vector<ksc::SimpBlock> b;
+  // chunks of 8 rows (half the registers of 16) while every chain fits
+  int longest = 0;
+  for (const CurveDev& d : p->cd) longest = std::max(longest, (d.n_s - 1) / 2);
+  if (longest > ksc::kSimpMaxChunks * ksc::kSimpChunkMax)
+    return fail(KSC_ERR_UNSUPPORTED, "ksc_set_scheme: n_s too large for the banded solve");
+  const int chunk = longest <= ksc::kSimpMaxChunks * 8 ? 8 : 16;
+  for (int c = 0; c < p->nc; ++c) {
+    const CurveDev& d = p->cd[c];
+    const int nm = p->row_elems(d);
+    int cw = 1;
+    while (cw < nm) cw *= 2;
+    for (int par = 0; par < 2; ++par) {
+      const int n = (d.n_s - 1 - par) / 2;
+      if (n < 1) continue;
+      int lp = 0;
+      while ((1 << lp) * chunk < n) ++lp;
+      while ((ksc::kSimpThreads >> lp) > cw) ++lp;
+      if ((1 << lp) > ksc::kSimpMaxChunks)
+        return fail(KSC_ERR_UNSUPPORTED, "ksc_set_scheme: too few mode columns");
+      const int CW = ksc::kSimpThreads >> lp;
+      for (int c0 = 0; c0 < nm; c0 += CW) b.push_back(ksc::SimpBlock{c, par, c0, lp});
+    }
+  }
+  if (p->d_simp) hipFree(p->d_simp);
+  p->d_simp = nullptr;
+  p->n_simp = int(b.size());
+  p->simp_chunk = chunk;
+  KSC_HIP(hipMalloc(&p->d_simp, b.size() * sizeof(ksc::SimpBlock)));
+  KSC_HIP(hipMemcpy(p->d_simp, b.data(), b.size() * sizeof(ksc::SimpBlock),
+                    hipMemcpyHostToDevice));
+  if (!p->d_G) KSC_HIP(hipMalloc(&p->d_G, p->state_bytes()));
+  return KSC_OK;
+}
+
+template <typename T>
+ksc_status launch_simp_t(ksc_problem* p, const void* in, void* out, double dtau,
+                         const uint8_t* active, hipStream_t s) {
+  ksc::SimpArgs<T> a{};
+  a.in = static_cast<const T*>(in);
+  a.grad = static_cast<const T*>(p->d_G);
+  a.out = static_cast<T*>(out);
+  a.curves = p->d_cd;
+  a.cs = static_cast<const T*>(p->d_cs);
+  a.wlT = static_cast<const T*>(p->d_wlT);
+  a.A = static_cast<const T*>(p->d_A);
+  a.blocks = p->d_simp;
+  a.active = active;
+  a.dtau = T(dtau);
+  a.odd = p->odd() ? 1 : 0;
+  hipError_t e;
+  if constexpr (sizeof(T) == 8)
+    e = ksc::launch_simp_f64(p->simp_chunk, p->n_simp, s, a);
+  else
+    e = ksc::launch_simp_f32(p->simp_chunk, p->n_simp, s, a);
+  if (e != hipSuccess) return fail(KSC_ERR_HIP, std::string("simp kernel: ") + hipGetErrorString(e));
+  return KSC_OK;
+}
+
+// One descent step in -> out under the problem's scheme.
+ksc_status step_once(ksc_problem* p, const void* in, void* out, double dtau,
+                     const uint8_t* active, double* J2, int track, bool finalize, hipStream_t s) {
+  if (p->scheme == KSC_SCHEME_PAPER)
+    return run(p, ksc::MODE_STEP, in, out, nullptr, active, J2, nullptr, track, finalize, s);
+  ksc_status st = run(p, ksc::MODE_GRAD, in, p->d_G, nullptr, active, J2, nullptr, track,
+                      finalize, s);
+  if (st != KSC_OK) return st;
+  return p->dtype == KSC_F64 ? launch_simp_t<double>(p, in, out, dtau, active, s)
+                             : launch_simp_t<float>(p, in, out, dtau, active, s);
+}
+
 template <typename T>
 std::vector<T> cast_vec(const std::vector<double>& v) {
   return std::vector<T>(v.begin(), v.end());
@@ -1131,7 +1217,7 @@ ksc_status ksc_destroy(ksc_problem* p) {
   void* bufs[] = {p->d_bounds, p->d_cd,  p->d_tiles, p->d_cs,    p->d_wlT,    p->d_wlD,
                   p->d_A,   p->d_pre,   p->d_sqrtL, p->d_part,   p->d_prevJ2,
                   p->d_flags, p->d_J2,  p->d_edge,  p->d_dpool,  p->d_spec,  p->d_Y,
-                  p->d_WR,  p->d_P,   p->d_sgroups, p->d_kpart};
+                  p->d_WR,  p->d_P,   p->d_sgroups, p->d_kpart, p->d_G, p->d_simp};
   for (void* b : bufs)
     if (b) hipFree(b);
   delete p;
@@ -1229,8 +1315,7 @@ ksc_status ksc_step(ksc_problem* p, const void* in, void* out, double dtau, doub
   if (!(dtau > 0) || !std::isfinite(dtau)) return fail(KSC_ERR_ARG, "ksc_step: dtau must be > 0");
   ksc_status st = ensure_pre(p, dtau, p->stream);
   if (st != KSC_OK) return st;
-  return run(p, ksc::MODE_STEP, in, out, nullptr, nullptr, J2, nullptr, 0, J2 != nullptr,
-             p->stream);
+  return step_once(p, in, out, dtau, nullptr, J2, 0, J2 != nullptr, p->stream);
 }
 
 // Record `every` steps (state -> scratch -> state ...) plus per-step
@@ -1244,7 +1329,7 @@ static ksc_status capture_descent(ksc_problem* p, void* state, void* scratch, do
   for (int i = 0; i < every && st == KSC_OK; ++i) {
     const void* in = (i % 2 == 0) ? state : scratch;
     void* out = (i % 2 == 0) ? scratch : state;
-    st = run(p, ksc::MODE_STEP, in, out, nullptr, active, p->d_J2, nullptr, 1, true, s);
+    st = step_once(p, in, out, dtau, active, p->d_J2, 1, true, s);
   }
   hipGraph_t g = nullptr;
   hipError_t e = hipStreamEndCapture(s, &g);
@@ -1301,11 +1386,33 @@ ksc_status ksc_descend(ksc_problem* p, void* state, void* scratch, int64_t n_ste
   for (int64_t i = 0; i < rem; ++i) {
     const void* in = (i % 2 == 0) ? state : scratch;
     void* out = (i % 2 == 0) ? scratch : state;
-    st = run(p, ksc::MODE_STEP, in, out, nullptr, active, p->d_J2, nullptr, 1, true, p->stream);
+    st = step_once(p, in, out, dtau, active, p->d_J2, 1, true, p->stream);
     if (st != KSC_OK) return st;
   }
   if (rem % 2 == 1)
     KSC_HIP(hipMemcpyAsync(state, scratch, p->state_bytes(), hipMemcpyDeviceToDevice, p->stream));
+  return KSC_OK;
+}
+
+ksc_status ksc_set_scheme(ksc_problem* p, int32_t scheme) {
+  if (!p) return fail(KSC_ERR_ARG, "ksc_set_scheme: null problem");
+  if (scheme != KSC_SCHEME_PAPER && scheme != KSC_SCHEME_IMPLICIT_S)
+    return fail(KSC_ERR_ARG, "ksc_set_scheme: bad scheme");
+  if (scheme == KSC_SCHEME_IMPLICIT_S) {
+    if (p->spectral())
+      return fail(KSC_ERR_UNSUPPORTED,
+                  "ksc_set_scheme: the implicit-in-s step needs the central-difference d/ds");
+    ksc_status st = build_simp(p);
+    if (st != KSC_OK) return st;
+  }
+  if (scheme != p->scheme) drop_graph(p);
+  p->scheme = scheme;
+  return KSC_OK;
+}
+
+ksc_status ksc_get_scheme(const ksc_problem* p, int32_t* scheme) {
+  if (!p || !scheme) return fail(KSC_ERR_ARG, "ksc_get_scheme: null pointer");
+  *scheme = p->scheme;
   return KSC_OK;
 }
 

@@ -456,14 +456,13 @@ __device__ __forceinline__ void spec_gemm_body(const SpecArgs<T>& sa, int count,
   double* Bs = lds + BK * SA;     // [BK][SB]
 
   double ra[AE], rb[BE];
-  // A tile element e of thread t: (i, kk) with i < 64, kk < BK; consecutive
-  // elements of a thread are consecutive in memory
+  // A tile element e of thread t: (i, kk) with i < 64, kk < BK
   auto a_index = [&](int e, int& i, int& kk) {
-    if constexpr (TRANS) {  // D~[k][i]: 64 consecutive i for each k
-      kk = t / (BM / AE);
-      i = (t % (BM / AE)) * AE + e;
-    } else {                // D~[i][k]: BK consecutive k for each i
-      i = t / (BK / AE);
+    if constexpr (TRANS) {  // D~[k][i]: a wave reads 64 consecutive i of one k and
+      i = t % BM;           // writes them to 64 consecutive LDS words
+      kk = (t / BM) * AE + e;
+    } else {                // D~[i][k]: consecutive elements of a thread are
+      i = t / (BK / AE);    // consecutive k of one row
       kk = (t % (BK / AE)) * AE + e;
     }
   };

@@ -83,6 +83,7 @@ class GpuBackend:
         from .problem import Problem
         p64 = Problem(self.prob.curves, dtype=self._torch.float64, device=self.state.device,
                       space=self.prob.space, ds=self.prob.ds)
+        p64.set_scheme(self.prob.scheme)
         b = GpuBackend(p64, self.state.double())
         b.active.copy_(self.active)
         return b
@@ -238,6 +239,9 @@ def main(argv=None):
                     help="start precision (default: f64 with --connection, else f32)")
     ap.add_argument("--jarc-target", type=float, default=None,
                     help="also stop a curve when J_arc falls below this (--connection: 1e-12)")
+    ap.add_argument("--scheme", default="paper", choices=["paper", "implicit_s"],
+                    help="descent step: the paper's (A_k^2 implicit) or implicit_s (the whole "
+                         "linear part, d/ds included, implicit: larger stable dtau)")
     ap.add_argument("--history", default=None,
                     help="write the J and J_arc records (per chunk) and the events to this JSON file")
     args = ap.parse_args(argv)
@@ -277,6 +281,7 @@ def main(argv=None):
         if any(np.abs(U.real).max() > 0 for U in Us):
             raise ValueError("the odd subspace needs inversion-symmetric curves (u_hat_k = i b_k)")
         Us = [np.ascontiguousarray(U[:, 1:].imag) for U in Us]
+    prob.set_scheme(args.scheme)
     prob.tune(None)
     X = prob.new_state()
     for c, U in enumerate(Us):
@@ -284,7 +289,8 @@ def main(argv=None):
     b = GpuBackend(prob, X)
     t0 = time.time()
     J0 = np.sqrt(b.J2())
-    print(f"start: {len(specs)} curves ({ds} d/ds, {space} space), J max {J0.max():.3e} "
+    print(f"start: {len(specs)} curves ({ds} d/ds, {space} space, {args.scheme} step), "
+          f"J max {J0.max():.3e} "
           f"min {J0.min():.3e}"
           + (f", J_arc {np.array2string(b.J_arc(), precision=3)}" if args.jarc_target else ""),
           flush=True)
@@ -327,7 +333,7 @@ def main(argv=None):
             json.dump({"curves": [f"{sp.n_x}x{sp.n_s} L={sp.L} S={sp.scale}" for sp in specs],
                        "labels": labels,
                        "connection": args.connection, "ds": ds, "space": space,
-                       "dtau0": args.dtau,
+                       "dtau0": args.dtau, "scheme": args.scheme,
                        "records": [{"step": st, "tau": st * args.dtau, "J": list(map(float, j)),
                                     "J_arc": arc.get(st)} for st, j in log.J_history],
                        "events": log.events}, fh)

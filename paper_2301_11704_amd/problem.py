@@ -235,6 +235,22 @@ class Problem:
     def set_launch(self, policy: int = _lib.KSC_LAUNCH_AUTO, waves: int = 0):
         check(lib().ksc_set_launch(self._h, int(policy), int(waves)))
 
+    SCHEMES = {"paper": _lib.KSC_SCHEME_PAPER, "implicit_s": _lib.KSC_SCHEME_IMPLICIT_S}
+
+    def set_scheme(self, scheme: str = "paper"):
+        """Descent scheme of later step / descend calls: "paper" (A_k^2
+        implicit) or "implicit_s" (the whole linear part, d/ds included,
+        implicit; include/ksc.h, ksc_set_scheme)."""
+        if scheme not in self.SCHEMES:
+            raise ValueError(f"unknown scheme {scheme!r}")
+        check(lib().ksc_set_scheme(self._h, self.SCHEMES[scheme]))
+
+    @property
+    def scheme(self) -> str:
+        v = ctypes.c_int32()
+        check(lib().ksc_get_scheme(self._h, ctypes.byref(v)))
+        return {b: a for a, b in self.SCHEMES.items()}[int(v.value)]
+
     @property
     def launch(self):
         p, w = ctypes.c_int32(), ctypes.c_int32()

@@ -48,6 +48,9 @@ def test_pure_host_calls():
     assert L.ksc_set_timing(None, 1) == -1
     f, q, n = ctypes.c_double(), ctypes.c_double(), ctypes.c_int64()
     assert L.ksc_read_timing(None, ctypes.byref(f), ctypes.byref(q), ctypes.byref(n)) == -1
+    sc = ctypes.c_int32()
+    assert L.ksc_set_scheme(None, 1) == -1
+    assert L.ksc_get_scheme(None, ctypes.byref(sc)) == -1
 
 
 def test_create_validates_before_touching_the_device():
