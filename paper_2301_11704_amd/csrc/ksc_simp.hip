@@ -122,8 +122,12 @@ __global__ __launch_bounds__(kSimpThreads) void simp_kernel(SimpArgs<T> a) {
   const T dfac = (T(1) + dtau * Ak * Ak) * inv2L;              // times wl_j = 2 w_j L
   const T rfac = -dtau * inv2L / ck;
 
-  // loads: right-hand sides and the metric of the chunk's rows
+  // loads: right-hand sides, states and the metric of the chunk's rows, all
+  // issued before the first use (the states only where registers allow:
+  // not for 16 FP64 rows)
+  constexpr bool PF = !(sizeof(T) == 8 && MM == 16);
   T y[MM][NV], wj[MM], bn[MM];
+  V xin[PF ? MM : 1];
   T bprev;  // beta of the row before the chunk's first row
   bprev = cs[j0 + 2 * min(q0, n - 1) - 1];
 #pragma unroll
@@ -132,6 +136,7 @@ __global__ __launch_bounds__(kSimpThreads) void simp_kernel(SimpArgs<T> a) {
     wj[i] = wl[j];
     bn[i] = cs[j + 1];
     const V g = vgr[eidx(j)];
+    if constexpr (PF) xin[i] = vin[eidx(j)];
 #pragma unroll
     for (int v = 0; v < NV; ++v) y[i][v] = g.v[v] * rfac;
   }
@@ -286,7 +291,11 @@ __global__ __launch_bounds__(kSimpThreads) void simp_kernel(SimpArgs<T> a) {
   for (int i = 0; i < MM; ++i) {
     if (i < mp) {
       const long long ix = eidx(j0 + 2 * (q0 + i));
-      V x = vin[ix];
+      V x;
+      if constexpr (PF)
+        x = xin[i];
+      else
+        x = vin[ix];
 #pragma unroll
       for (int v = 0; v < NV; ++v)
         x.v[v] += (i < mi) ? y[i][v] + l[i] * s_left[v] + r[i] * s_me[v] : s_me[v];
