@@ -258,7 +258,9 @@ ksc_status ksc_query_flags(ksc_problem* p, uint32_t* flags_host);
  * stream has its kernel dispatches stamp HIP events (hipExtLaunchKernelGGL
  * start/stop events): the start and end of the fused tile kernel(s) and of
  * the post kernel.
- * Calls made under stream capture and ksc_descend's graphs are not timed.
+ * Calls made under stream capture and ksc_descend's graphs are not timed;
+ * under KSC_SCHEME_IMPLICIT_S a ksc_step's record covers its gradient
+ * evaluation, not the banded solve that follows it.
  * enable == 0 stops recording (the window keeps what it holds).  At most
  * 65536 evaluations per window; later ones are not timed and
  * ksc_read_timing reports KSC_ERR_STATE. */

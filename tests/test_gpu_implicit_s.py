@@ -221,3 +221,21 @@ def test_large_step_descends_on_the_64_curve_batch_shape():
     tr = prob.descend(X, 200, 0.01, every=1).cpu().numpy()
     assert np.all(np.isfinite(tr))
     assert np.all(np.diff(tr, axis=0) < 0), tr[:5]
+
+
+def test_driver_promotion_keeps_the_scheme():
+    """The descent driver's FP32 -> FP64 promotion continues with the same
+    scheme (and the FP64 step of the promoted problem matches the oracle)."""
+    from paper_2301_11704_amd.driver import GpuBackend
+    spec = ksinputs.config_specs(0)[0]
+    prob = _problem([spec], np.float32)
+    X = prob.new_state()
+    U = seeded_state(spec, np.float32)
+    prob.upload(X, 0, U)
+    b64 = GpuBackend(prob, X).promote()
+    assert b64.prob.scheme == "implicit_s"
+    Y = torch.empty_like(b64.state)
+    b64.prob.step(b64.state, Y, 0.02)
+    torch.cuda.synchronize()
+    ref = oracle.step_implicit_s(oracle_curve(spec), U, 0.02)
+    _check(b64.prob.download(Y, 0), ref, U, np.float64)
