@@ -31,7 +31,7 @@ __device__ __forceinline__ SpecTile spec_tile(const SpecGroupDev* __restrict__ g
 }
 
 template <typename T, int NCP, bool TRANS, int EPI, bool ODD>
-__global__ __launch_bounds__(256) void spec_gemm_kernel(SpecArgs<T> sa,
+__global__ __launch_bounds__(256, 3) void spec_gemm_kernel(SpecArgs<T> sa,
                                                         const SpecGroupDev* __restrict__ groups,
                                                         int n_groups) {
   __shared__ __align__(16) double lds[spec_gemm_lds<NCP>()];
