@@ -455,7 +455,10 @@ __device__ __forceinline__ void spec_gemm_body(const SpecArgs<T>& sa, int count,
   double* As = lds;               // [BK][SA]
   double* Bs = lds + BK * SA;     // [BK][SB]
 
-  double ra[AE], rb[BE];
+  // B is held in the state's dtype until it is written to LDS, so that an
+  // FP32 state's conversion does not wait on its load right after issuing it
+  double ra[AE];
+  T rb[BE];
   // A tile element e of thread t: (i, kk) with i < 64, kk < BK
   auto a_index = [&](int e, int& i, int& kk) {
     if constexpr (TRANS) {  // D~[k][i]: a wave reads 64 consecutive i of one k and
@@ -487,7 +490,7 @@ __device__ __forceinline__ void spec_gemm_body(const SpecArgs<T>& sa, int count,
       long long o = -1;
 #pragma unroll
       for (int x = 0; x < CB; ++x) o = (cb == x) ? boff[x] : o;
-      rb[e] = (gk < n_s && col < NC && o >= 0) ? double(sa.b[o + (long long)gk * NC + col]) : 0.0;
+      rb[e] = (gk < n_s && col < NC && o >= 0) ? sa.b[o + (long long)gk * NC + col] : T(0);
     }
   };
   auto store = [&]() {
@@ -500,7 +503,7 @@ __device__ __forceinline__ void spec_gemm_body(const SpecArgs<T>& sa, int count,
 #pragma unroll
     for (int e = 0; e < BE; ++e) {
       const int q = t + 256 * e;
-      Bs[(q / BW) * SB + q % BW] = rb[e];  // [kk][cb*NCP + col]
+      Bs[(q / BW) * SB + q % BW] = double(rb[e]);  // [kk][cb*NCP + col]
     }
   };
 
