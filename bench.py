@@ -208,7 +208,9 @@ def cpu_baseline(specs, Us, budget_s=12.0, single_s=6.0):
     with cf.ProcessPoolExecutor(max_workers=workers, mp_context=mp.get_context("spawn")) as ex:
         list(ex.map(_oracle_eval, tasks[:workers]))  # start-up and imports, not timed
         t0 = time.perf_counter()
-        pts = sum(ex.map(_oracle_eval, tasks, chunksize=1))
+        # chunks of tasks per hand-off, so that inter-process traffic does not
+        # dominate the few-millisecond tasks
+        pts = sum(ex.map(_oracle_eval, tasks, chunksize=max(1, n_tasks // (8 * workers))))
         el = time.perf_counter() - t0
     return {
         "value": pts / el, "unit": "curve-point evals/s", "cores": workers, "kind": "oracle",
