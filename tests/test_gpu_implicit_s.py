@@ -239,3 +239,29 @@ def test_driver_promotion_keeps_the_scheme():
     torch.cuda.synchronize()
     ref = oracle.step_implicit_s(oracle_curve(spec), U, 0.02)
     _check(b64.prob.download(Y, 0), ref, U, np.float64)
+
+
+def test_64_curve_batch_sampled_against_the_oracle():
+    """The benchmark's 64-curve batch (N_x = 128, N_s = 1024, FP32) with the
+    tuned launch: one implicit-in-s step at dtau = 0.05 for every curve, two
+    sampled curves checked against the oracle's dense solves."""
+    import os
+    import paper_2301_11704_amd as ksc
+    specs, Us = ksinputs.config4_curves(64, 1024)
+    prob = _problem(specs, np.float32)
+    prob.tune(os.path.join(os.path.dirname(ksc.__file__), "tuning_gfx950.json"))
+    X = prob.new_state()
+    Ur = []
+    for i, U in enumerate(Us):
+        U = ksinputs.round_to(U, np.float32)
+        U[:, 0] = U[:, 0].real
+        prob.upload(X, i, U)
+        Ur.append(U)
+    Y = torch.empty_like(X)
+    prob.step(X, Y, 0.05)
+    torch.cuda.synchronize()
+    for i in (0, 63):
+        got = prob.download(Y, i)
+        ref = oracle.step_implicit_s(oracle_curve(specs[i]), Ur[i], 0.05)
+        err, inc = _check(got, ref, Ur[i], np.float32)
+        print(f"batch curve {i}: state-relative {err:.2e} increment-relative {inc:.2e}", flush=True)

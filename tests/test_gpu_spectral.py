@@ -299,3 +299,29 @@ def test_spectral_odd_descent_matches_full_space():
     assert np.abs(uf.real).max() <= 1e-14 * np.abs(uf).max()
     assert np.linalg.norm(bo - uf[:, 1:].imag) <= 60 * TOL[np.float64] * np.linalg.norm(bo)
     assert np.allclose(to.cpu().numpy(), tf.cpu().numpy(), rtol=60 * TOL[np.float64], atol=0)
+
+
+def test_spectral_paper_shape_batch_in_the_bench_configuration():
+    """The 64-curve paper-shape batch (N_x = 64, N_s = 552, S = 55; FP32 state)
+    with the launch shape the benchmark uses: J2 of every curve, and the
+    gradient and a step of three sampled curves, against the oracle."""
+    import os
+    import paper_2301_11704_amd as ksc
+    specs = ksinputs.paper_shape_specs(64)
+    prob = ksc.Problem([ksc.CurveDesc(s.n_s, s.n_x, s.L, s.map, s.scale, s.s0) for s in specs],
+                       dtype=torch.float32, ds="spectral")
+    prob.tune(os.path.join(os.path.dirname(ksc.__file__), "tuning_gfx950.json"))
+    X = prob.new_state()
+    Us = []
+    for i, s in enumerate(specs):
+        U = ksinputs.round_to(ksinputs.make_curve(s, (s.n_x - 1) // 3 + 1)[2], np.float32)
+        U[:, 0] = U[:, 0].real
+        prob.upload(X, i, U)
+        Us.append(U)
+    J2 = prob.eval_J(X).cpu().numpy()
+    for i, s in enumerate(specs):
+        ref = oracle.J2(_curve(s), Us[i])
+        assert abs(J2[i] - ref) <= TOL[np.float32] * ref, (i, J2[i], ref)
+    for i in (0, 31, 63):
+        print(f"paper-shape batch, curve {i}", flush=True)
+        _check(prob, X, _curve(specs[i]), Us[i], np.float32, i=i, dtau=0.01)
