@@ -469,6 +469,13 @@ __device__ __forceinline__ void spec_gemm_body(const SpecArgs<T>& sa, int count,
       kk = (t % (BK / AE)) * AE + e;
     }
   };
+  // A-tile column swizzle.  Untransposed, the four lanes that write one row i
+  // of a k step hold k = e, e+8, e+16, e+24: swapping the 16-row halves for
+  // odd k/8 puts two of them in the other half of the banks (2-way instead of
+  // 4-way store conflicts).  The product reads take one k/8 block per step,
+  // so they see the same permutation for every 16-lane group and stay
+  // conflict-free.  The transposed tile is stored in row order already.
+  auto aswz = [&](int kk, int i) { return TRANS ? i : (i ^ (16 * ((kk >> 3) & 1))); };
   auto load = [&](int k0) {
     // A tile: op(D~)[row0 + i][k0 + kk]
 #pragma unroll
@@ -498,7 +505,7 @@ __device__ __forceinline__ void spec_gemm_body(const SpecArgs<T>& sa, int count,
     for (int e = 0; e < AE; ++e) {
       int i, kk;
       a_index(e, i, kk);
-      As[kk * SA + i] = ra[e];
+      As[kk * SA + aswz(kk, i)] = ra[e];
     }
 #pragma unroll
     for (int e = 0; e < BE; ++e) {
@@ -523,7 +530,7 @@ __device__ __forceinline__ void spec_gemm_body(const SpecArgs<T>& sa, int count,
 #pragma unroll
     for (int s = 0; s < BK / 4; ++s) {
       const int kk = 4 * s + (lane >> 4);
-      const double av = As[kk * SA + 16 * w + (lane & 15)];
+      const double av = As[kk * SA + aswz(kk, 16 * w + (lane & 15))];
 #pragma unroll
       for (int j = 0; j < NJ; ++j) {
         const double bv = Bs[kk * SB + 16 * j + (lane & 15)];
