@@ -157,9 +157,10 @@ ksc_status ksc_create2(const ksc_curve_desc* descs, int32_t n_curves, int32_t dt
 /* The same with every option (opts: host pointer).  KSC_DS_SPECTRAL (either
  * space) needs the rational map on every curve, one row per lane: n_x <= 128
  * in FP32, n_x <= 64 in FP64, and n_s <= 16384 (KSC_ERR_UNSUPPORTED or
- * KSC_ERR_ARG otherwise, before any device work).  It allocates D_t for every
- * distinct n_s (n_s^2 FP64 scalars), three state-sized work arrays and, for
- * small batches, FP64 partial products of up to 8 state sizes. */
+ * KSC_ERR_ARG otherwise, before any device work).  It allocates D_t and its
+ * transpose for every distinct n_s (2 n_s^2 FP64 scalars), three state-sized
+ * work arrays and, for small batches, FP64 partial products of up to 8 state
+ * sizes. */
 ksc_status ksc_create_opts(const ksc_curve_desc* descs, int32_t n_curves, const ksc_options* opts,
                            void* hip_stream, ksc_problem** out);
 ksc_status ksc_destroy(ksc_problem* p);

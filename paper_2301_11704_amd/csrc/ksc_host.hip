@@ -794,13 +794,18 @@ ksc_status setup_spectral(ksc_problem* p) {
   long long total = 0;
   for (size_t i = 0; i < sizes.size(); ++i) {
     moff[i] = total;
-    total += (long long)sizes[i] * sizes[i];
+    total += 2 * (long long)sizes[i] * sizes[i];  // D~, then its transpose
   }
   KSC_HIP(hipMalloc(&p->d_dpool, size_t(total) * sizeof(double)));  // FP64 for both dtypes
   for (size_t i = 0; i < sizes.size(); ++i) {
-    std::vector<double> D = make_dtilde(sizes[i]);
-    KSC_HIP(hipMemcpy(static_cast<double*>(p->d_dpool) + moff[i], D.data(), D.size() * 8,
-                      hipMemcpyHostToDevice));
+    const int n = sizes[i];
+    std::vector<double> D = make_dtilde(n);
+    std::vector<double> DT(D.size());
+    for (int r = 0; r < n; ++r)
+      for (int q = 0; q < n; ++q) DT[size_t(q) * n + r] = D[size_t(r) * n + q];
+    double* dst = static_cast<double*>(p->d_dpool) + moff[i];
+    KSC_HIP(hipMemcpy(dst, D.data(), D.size() * 8, hipMemcpyHostToDevice));
+    KSC_HIP(hipMemcpy(dst + size_t(n) * n, DT.data(), DT.size() * 8, hipMemcpyHostToDevice));
   }
   std::vector<SpecDev> sd;
   p->spec_groups.clear();
@@ -815,6 +820,7 @@ ksc_status setup_spectral(ksc_problem* p) {
     SpecDev s{};
     s.off = d.off;
     s.dmat = moff[mi];
+    s.dmatT = moff[mi] + (long long)d.n_s * d.n_s;
     s.n_s = d.n_s;
     s.km = d.km;
     s.row_off = d.row_off;

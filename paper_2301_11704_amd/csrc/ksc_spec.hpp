@@ -31,6 +31,7 @@ namespace ksc {
 struct SpecDev {
   long long off;   // offset of row 0 in complex elements of the state
   long long dmat;  // offset of the curve's D~ (n_s x n_s, row-major) in the matrix pool
+  long long dmatT; // offset of its transpose
   int n_s, km, row_off, mode_off;
   int c, pad_;     // index of the curve in the problem
   double inv_S;    // 1 / S
@@ -447,7 +448,10 @@ __device__ __forceinline__ void spec_gemm_body(const SpecArgs<T>& sa, int count,
   const SpecDev c0 = sa.curves[cbase];
   const int n_s = c0.n_s;
   const int NC = spec_cols<ODD>(c0);
-  const double* __restrict__ D = sa.dpool + c0.dmat;
+  // op(D~)[i][k] is read as M[k][i] from M = D~^T (untransposed product) or
+  // M = D~ (transposed product): a wave reads 64 consecutive doubles of one
+  // row of M and writes them to 64 consecutive LDS words
+  const double* __restrict__ D = sa.dpool + (TRANS ? c0.dmat : c0.dmatT);
   long long boff[CB];  // scalar offset of each curve's state block, -1 past the group
 #pragma unroll
   for (int cb = 0; cb < CB; ++cb)
@@ -461,21 +465,9 @@ __device__ __forceinline__ void spec_gemm_body(const SpecArgs<T>& sa, int count,
   T rb[BE];
   // A tile element e of thread t: (i, kk) with i < 64, kk < BK
   auto a_index = [&](int e, int& i, int& kk) {
-    if constexpr (TRANS) {  // D~[k][i]: a wave reads 64 consecutive i of one k and
-      i = t % BM;           // writes them to 64 consecutive LDS words
-      kk = (t / BM) * AE + e;
-    } else {                // D~[i][k]: consecutive elements of a thread are
-      i = t / (BK / AE);    // consecutive k of one row
-      kk = (t % (BK / AE)) * AE + e;
-    }
+    i = t % BM;
+    kk = (t / BM) * AE + e;
   };
-  // A-tile column swizzle.  Untransposed, the four lanes that write one row i
-  // of a k step hold k = e, e+8, e+16, e+24: swapping the 16-row halves for
-  // odd k/8 puts two of them in the other half of the banks (2-way instead of
-  // 4-way store conflicts).  The product reads take one k/8 block per step,
-  // so they see the same permutation for every 16-lane group and stay
-  // conflict-free.  The transposed tile is stored in row order already.
-  auto aswz = [&](int kk, int i) { return TRANS ? i : (i ^ (16 * ((kk >> 3) & 1))); };
   auto load = [&](int k0) {
     // A tile: op(D~)[row0 + i][k0 + kk]
 #pragma unroll
@@ -484,7 +476,7 @@ __device__ __forceinline__ void spec_gemm_body(const SpecArgs<T>& sa, int count,
       a_index(e, i, kk);
       const int gi = row0 + i, gk = k0 + kk;
       double v = 0.0;
-      if (gi < n_s && gk < n_s) v = TRANS ? D[(long long)gk * n_s + gi] : D[(long long)gi * n_s + gk];
+      if (gi < n_s && gk < n_s) v = D[(long long)gk * n_s + gi];
       ra[e] = v;
     }
     // B tile: row k0 + kk of each curve's n_s x NC block, curves side by side
@@ -505,7 +497,7 @@ __device__ __forceinline__ void spec_gemm_body(const SpecArgs<T>& sa, int count,
     for (int e = 0; e < AE; ++e) {
       int i, kk;
       a_index(e, i, kk);
-      As[kk * SA + aswz(kk, i)] = ra[e];
+      As[kk * SA + i] = ra[e];
     }
 #pragma unroll
     for (int e = 0; e < BE; ++e) {
@@ -530,7 +522,7 @@ __device__ __forceinline__ void spec_gemm_body(const SpecArgs<T>& sa, int count,
 #pragma unroll
     for (int s = 0; s < BK / 4; ++s) {
       const int kk = 4 * s + (lane >> 4);
-      const double av = As[kk * SA + aswz(kk, 16 * w + (lane & 15))];
+      const double av = As[kk * SA + 16 * w + (lane & 15)];
 #pragma unroll
       for (int j = 0; j < NJ; ++j) {
         const double bv = Bs[kk * SB + 16 * j + (lane & 15)];
