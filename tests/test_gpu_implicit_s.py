@@ -265,3 +265,19 @@ def test_64_curve_batch_sampled_against_the_oracle():
         ref = oracle.step_implicit_s(oracle_curve(specs[i]), Ur[i], 0.05)
         err, inc = _check(got, ref, Ur[i], np.float32)
         print(f"batch curve {i}: state-relative {err:.2e} increment-relative {inc:.2e}", flush=True)
+
+
+def test_driver_cli_runs_the_implicit_scheme(tmp_path, capsys):
+    """The descent driver's command line with --scheme implicit_s: a short run
+    of four batch curves at dtau = 0.05 lowers every curve's J."""
+    import json
+    from paper_2301_11704_amd import driver
+    hist = tmp_path / "h.json"
+    driver.main(["--scheme", "implicit_s", "--dtau", "0.05", "--curves", "4", "--max-steps", "400",
+                 "--chunk", "200", "--every", "100", "--history", str(hist)])
+    out = capsys.readouterr().out
+    assert "implicit_s step" in out
+    h = json.loads(hist.read_text())
+    assert h["scheme"] == "implicit_s"
+    J0, J1 = np.array(h["records"][0]["J"]), np.array(h["records"][-1]["J"])
+    assert np.all(J1 < J0), (J0, J1)
