@@ -1,0 +1,67 @@
+"""GPU rerun of the oracle's symmetry invariants (translation and inversion,
+eqs. translation and reflection): J2 computed by the HIP path is invariant
+and its gradient is equivariant, to the run tolerance (FP32 1e-5, FP64
+1e-12 relative).  A phase or sign error in the kernels' handling of the
+Fourier modes would break these even where a parity case happened to pass."""
+import numpy as np
+import pytest
+
+import ksinputs
+from helpers import seeded_state
+
+torch = pytest.importorskip("torch")
+
+pytestmark = pytest.mark.gpu
+
+TOL = {np.float32: 1e-5, np.float64: 1e-12}
+
+
+def _spec(n_s, n_x, seed):
+    kmax = min(6, (n_x - 1) // 3)
+    return ksinputs.CurveSpec(n_s, n_x, 22.0, kmax, 1.0, kmax, 0.2, True, seed, "rational", 40.0)
+
+
+def _translate(U, q, a):
+    """u(x) -> u(x + a): u_hat_k -> u_hat_k exp(i q_k a)."""
+    return U * np.exp(1j * q[None, :] * a)
+
+
+def _invert(U):
+    """u(x) -> -u(-x): u_hat_k -> -conj(u_hat_k)."""
+    return -np.conj(U)
+
+
+@pytest.mark.parametrize("dtype,ds", [(np.float64, "stencil"), (np.float32, "stencil"),
+                                      (np.float64, "spectral")])
+def test_cost_invariant_and_gradient_equivariant(dtype, ds):
+    import paper_2301_11704_amd as ksc
+    spec = _spec(97, 64, (130, 0))
+    U = seeded_state(spec, np.float64)
+    q = 2 * np.pi * np.arange(U.shape[1]) / spec.L
+    a = 0.37 * spec.L
+    variants = [U, _translate(U, q, a), _invert(U)]
+    # the transformed states are rounded to the run dtype as the originals are
+    variants = [ksinputs.round_to(V, dtype) for V in variants]
+    for V in variants:
+        V[:, 0] = V[:, 0].real
+    prob = ksc.Problem([ksc.CurveDesc(spec.n_s, spec.n_x, spec.L, spec.map, spec.scale, spec.s0)] * 3,
+                       dtype=torch.float32 if dtype == np.float32 else torch.float64, ds=ds)
+    X = prob.new_state()
+    for i, V in enumerate(variants):
+        prob.upload(X, i, V)
+    G, J2 = prob.eval_grad(X)
+    torch.cuda.synchronize()
+    J2 = J2.cpu().numpy()
+    tol = TOL[dtype]
+    assert abs(J2[1] - J2[0]) <= tol * J2[0], (J2[0], J2[1])
+    assert abs(J2[2] - J2[0]) <= tol * J2[0], (J2[0], J2[2])
+    G0, G1, G2 = (prob.download(G, i) for i in range(3))
+    # weigh the error like the other gradient gates: 1/(1 + A_k^2) per mode
+    Ak = q ** 2 - q ** 4
+    P = 1.0 / (1.0 + Ak ** 2)
+
+    def rel(Gt, Gr):
+        return np.linalg.norm((Gt - Gr) * P) / np.linalg.norm(Gr * P)
+
+    assert rel(G1, _translate(G0, q, a)) <= 10 * tol
+    assert rel(G2, _invert(G0)) <= 10 * tol
