@@ -7,18 +7,21 @@ boundary rows and the FP64 per-curve cost).  Workload (default): 64 curves,
 L = 66, N_x = 128 (43 kept modes), N_s = 1024, finite map T = 20, FP32 with
 FP64 cost reduction; endpoints are stored KS-trajectory states, the interior
 is the blend plus a seeded perturbation.  --workload c1/c2/c3 selects the
-single-curve and uneven-batch shapes, --dtype f64 the FP64 finish, --space odd
-the inversion-symmetric subspace (the same curves' sine coefficients
-b_k = Im u_hat_k).
+single-curve and uneven-batch shapes, p22 the paper-shape batch (64 curves,
+L = 22, N_x = 64, N_s = 552, rational map S = 55), --dtype f64 the FP64
+finish, --space odd the inversion-symmetric subspace (the same curves' sine
+coefficients b_k = Im u_hat_k), --ds spectral the rational-Chebyshev d/ds
+(then the roofline is the FP64 matrix-core one of the D_t products).
 
 Prints one JSON line.  value = curve-point evals/s = sum_c (N_s - 2) * steps / s
 over K timed steps; the roofline block uses the fused kernel's own duration
 from HIP events recorded by the library around each launch (a second window
 of K steps).  Extra legs: the plain policy (one launch per curve), the fused
 descent step, the captured-graph descent loop, autograd forward+backward, the
-streaming roofline (the batch replicated past the 256 MB last-level cache) and
-the same curves in the inversion-symmetric subspace, and the FP64 oracle
-timed on the host on a bounded sample.
+streaming roofline (the batch replicated past the 256 MB last-level cache),
+the same curves in the inversion-symmetric subspace, the descent step with
+the s-part implicit (banded solves), the paper-shape batch with the spectral
+d/ds, and the FP64 oracle timed on the host on a bounded sample.
 """
 from __future__ import annotations
 
