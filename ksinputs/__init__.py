@@ -212,26 +212,46 @@ TABLE2 = [
     (4, "E1", "E2", 550, 55.0), (5, "E1", "E3", 500, 60.0), (6, "E2", "E2+L/4", 400, 35.0),
     (7, "E2", "E3", 450, 50.0), (8, "E3", "E2", 600, 50.0), (9, "E3", "E2", 500, 40.0),
 ]
-# The destinations' other inversion-symmetric copies (about x = 0): E1 shifted
-# by L/2, E2 by L/4, E3 by L/6.
+# Each equilibrium's other inversion-symmetric copy (about x = 0): E1 shifted
+# by L/2, E2 by L/4, E3 by L/6; and its translation period in units of L.
 OTHER_PHASE = {"E1": "E1+L/2", "E2": "E2+L/4", "E2+L/4": "E2", "E3": "E3+L/6", "E0": None}
+_SHIFT = {"E1": 0.0, "E1+L/2": 0.5, "E2": 0.0, "E2+L/4": 0.25, "E3": 0.0, "E3+L/6": 1.0 / 6.0}
+_PERIOD = {"E1": 1.0, "E2": 0.5, "E3": 1.0 / 3.0}
+
+
+def _phase_class(a: str, b: str) -> float:
+    """The relative shift of destination against source, modulo the shifts
+    that map either equilibrium to itself (a connection and its common
+    translation are the same run)."""
+    pa, pb = _PERIOD[a.split("+")[0]], _PERIOD[b.split("+")[0]]
+    # the smallest positive combination of the two periods (both are 1/n)
+    g = 1.0 / np.lcm(int(round(1 / pa)), int(round(1 / pb)))
+    return round((_SHIFT[b] - _SHIFT[a]) % g, 9) % g
 
 
 def table2_connections(both_phases: bool = True):
     """Initial curves (eq. KSE_initial_curve, a = 0) for the rows of Table II:
-    a list of (label, CurveSpec, U_hat).  With both_phases, every row whose
-    destination has another inversion-symmetric copy appears once more with
-    that copy (the table does not print the relative phase; rows from E0 have
-    no distinct phases).  Row 6 with a = 0 is the run the paper reports stuck
-    at a local minimum."""
+    a list of (label, CurveSpec, U_hat).  With both_phases, a row whose two
+    equilibria have another relative phase that keeps the curve
+    inversion-symmetric (the table does not print it) appears once more with
+    it: the destination's other copy, or the source's when that copy is
+    equivalent (E2 -> E3 and E2 -> E3 + L/6 differ by a symmetry of E3 and a
+    common shift).  Rows from E0 have no distinct phases; row 6 with a = 0 is
+    the run the paper reports stuck at a local minimum."""
     out = []
     for row, a, b, M, S in TABLE2:
-        # E0 is translation invariant (every phase of the destination is
-        # equivalent), and row 6 connects E2 to its own shifted copy
-        other = OTHER_PHASE.get(b) if (both_phases and a != "E0" and row != 6) else None
-        for dst in ([b, other] if other else [b]):
-            spec, U = l22_connection_curve(a, dst, M + 2, S)
-            out.append((f"row{row}:{a}->{dst}", spec, U))
+        pairs = [(a, b)]
+        if both_phases and a != "E0" and row != 6:
+            seen = {_phase_class(a, b)}
+            for cand in ((a, OTHER_PHASE[b]), (OTHER_PHASE[a], b)):
+                c = _phase_class(*cand)
+                if c not in seen:
+                    seen.add(c)
+                    pairs.append(cand)
+                    break
+        for src, dst in pairs:
+            spec, U = l22_connection_curve(src, dst, M + 2, S)
+            out.append((f"row{row}:{src}->{dst}", spec, U))
     return out
 
 

@@ -94,3 +94,31 @@ def test_initial_curve_and_spectral_descent_from_E1_to_E2():
         J.append(oracle.J2(c, U))
     assert np.all(np.diff(J) < 0) and J[-1] < 0.6 * J[0]
     assert np.abs(U.real).max() < 1e-12  # the descent keeps the subspace
+
+
+def test_table2_phase_variants_are_distinct_runs():
+    """The Table II initial curves: every one is inversion symmetric, and the
+    second curve of a row is a different run, not the first one moved by a
+    common translation.  For row 7 the destination's other copy would not be:
+    shifting E2 and E3 + L/6 both by L/2 gives E2 and E3 (E2 repeats after
+    L/2 and E3 after L/3), so the row varies its source instead."""
+    import ksinputs
+    made = ksinputs.table2_connections()
+    labels = [m[0] for m in made]
+    assert len(made) == 14 and "row7:E2+L/4->E3" in labels and "row7:E2->E3+L/6" not in labels
+    for _, _, U in made:
+        assert np.abs(U.real).max() < 1e-12 and np.all(U[:, 0] == 0)
+    k = np.arange(22)
+
+    def shift(U, frac):
+        return U * np.exp(2j * np.pi * k * frac)
+
+    E2, E3 = ksinputs.l22_equilibrium("E2"), ksinputs.l22_equilibrium("E3")
+    E3b = ksinputs.l22_equilibrium("E3+L/6")
+    assert np.allclose(shift(E2, 0.5), E2, atol=1e-10)
+    assert np.allclose(shift(E3b, 0.5), E3, atol=1e-10)
+    # while E2 + L/4 -> E3 is no common translation of E2 -> E3
+    E2b = ksinputs.l22_equilibrium("E2+L/4")
+    for frac in np.arange(12) / 12:
+        assert not (np.allclose(shift(E2b, frac), E2, atol=1e-6)
+                    and np.allclose(shift(E3, frac), E3, atol=1e-6))
