@@ -58,6 +58,7 @@ CASES = [  # n_s, n_x, map, scale, dtau: chains of 1 row, ragged chunk counts, u
     (300, 128, "finite", 20.0, 0.01),
     (1100, 32, "finite", 20.0, 0.05),
     (300, 256, "rational", 40.0, 1e-3),
+    (257, 32, "finite", 5.0, 1.0),  # 700x the explicit bound of the s-part (dtau beta^2 = 655)
 ]
 
 
