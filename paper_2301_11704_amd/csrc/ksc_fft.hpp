@@ -156,8 +156,10 @@ __device__ __forceinline__ void fft_c(T (&re)[M], T (&im)[M]) {
 //   x_n = sum_{|k|<=K} X_k e^{2 pi i k n / N},  X_{-k} = conj(X_k), Im X_0 ignored.
 // X has KM = K+1 entries; out has N entries.
 // ---------------------------------------------------------------------------
-template <int N, int KM, typename T>
-__device__ __forceinline__ void spec_to_phys(const cplx<T> (&X)[KM], T (&out)[N]) {
+// TI is the storage type of the coefficients (converted to the arithmetic
+// type T as they are read).
+template <int N, int KM, typename T, typename TI = T>
+__device__ __forceinline__ void spec_to_phys(const cplx<TI> (&X)[KM], T (&out)[N]) {
   constexpr int M = N / 2;
   static_assert(KM - 1 < M, "K must be below N/2");
   T zr[M], zi[M];
@@ -169,15 +171,16 @@ __device__ __forceinline__ void spec_to_phys(const cplx<T> (&X)[KM], T (&out)[N]
     constexpr int kb = M - k;  // partner index; kb == M means X_M (zero)
     T ar = T(0), ai = T(0), br = T(0), bi = T(0);
     if constexpr (k < KM) {
-      ar = X[k].r;
-      ai = (k == 0) ? T(0) : X[k].i;
+      ar = T(X[k].r);
+      ai = (k == 0) ? T(0) : T(X[k].i);
     }
     if constexpr (kb < KM) {
-      br = X[kb].r;
-      bi = -X[kb].i;  // conj
+      br = T(X[kb].r);
+      bi = -T(X[kb].i);  // conj
     }
-    T er = ar + br, ei = ai + bi;
-    T dr = ar - br, di = ai - bi;
+    // (a partner above K is zero: its sums and differences are not formed)
+    T er = (kb < KM) ? ar + br : ar, ei = (kb < KM) ? ai + bi : ai;
+    T dr = (kb < KM) ? ar - br : ar, di = (kb < KM) ? ai - bi : ai;
     T orr, oi;
     if constexpr (k == 0) {
       orr = dr;
@@ -305,8 +308,8 @@ __device__ __forceinline__ void cmul_unit(T& xr, T& xi) {
 // of the two results (never a select between two constants, which would keep
 // the constants in registers across the caller's loops).  pf passes through an
 // empty asm statement so that nothing derived from it is hoisted either.
-template <int N, int KH, typename T>
-__device__ __forceinline__ void spec_to_phys_pair(const cplx<T> (&X)[KH], T pf, T (&out)[N / 2]) {
+template <int N, int KH, typename T, typename TI = T>
+__device__ __forceinline__ void spec_to_phys_pair(const cplx<TI> (&X)[KH], T pf, T (&out)[N / 2]) {
   constexpr int M = N / 2, Q = M / 2;
   static_assert(2 * KH <= M + 1, "K must be below N/2");
   __asm__ volatile("" : "+v"(pf));
@@ -319,18 +322,18 @@ __device__ __forceinline__ void spec_to_phys_pair(const cplx<T> (&X)[KH], T pf, 
     constexpr int ib0 = Q - k1, ib1 = Q - k1 - 1;
     T ar = T(0), ai = T(0);
     if constexpr (k1 < KH) {
-      ar = X[k1].r;
-      ai = X[k1].i;
+      ar = T(X[k1].r);
+      ai = T(X[k1].i);
       if constexpr (k1 == 0) ai = odd ? ai : T(0);  // Im X_0 (lane 0, entry 0)
     }
     T b0r = T(0), b0i = T(0), b1r = T(0), b1i = T(0);
     if constexpr (ib0 < KH && ib0 < Q) {
-      b0r = X[ib0].r;
-      b0i = X[ib0].i;
+      b0r = T(X[ib0].r);
+      b0i = T(X[ib0].i);
     }
     if constexpr (ib1 < KH) {
-      b1r = X[ib1].r;
-      b1i = X[ib1].i;
+      b1r = T(X[ib1].r);
+      b1i = T(X[ib1].i);
     }
     const T br = odd ? b1r : b0r, bi = -(odd ? b1i : b0i);  // conj(X_{M-k})
     const T er = ar + br, ei = ai + bi;

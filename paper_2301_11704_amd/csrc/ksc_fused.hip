@@ -40,15 +40,18 @@ __global__ __launch_bounds__(64 * W) void mixed_kernel(KernelArgs<T> a) {
     const int tile = a.tile_base + i;
     const TileDev td = a.tiles[tile];
     const CurveDev cd = a.curves[td.curve];
+    // the tile's grid size is the same on every lane: branch on it as a
+    // wave-uniform (scalar) value, not as a per-lane condition
+    const int nx = __builtin_amdgcn_readfirstlane(cd.n_x);
     if (MODE == MODE_STEP && a.active != nullptr && a.active[td.curve] == 0) {
-      switch (cd.n_x) {
+      switch (nx) {
         case 32: tile_copy<32, T, W>(a, cd, td.curve, td.j0, tile); break;
         case 64: tile_copy<64, T, W>(a, cd, td.curve, td.j0, tile); break;
         default: tile_copy<128, T, W>(a, cd, td.curve, td.j0, tile); break;
       }
       continue;
     }
-    switch (cd.n_x) {
+    switch (nx) {
       case 32: tile_body<32, T, W, MODE>(a, cd, td.curve, td.j0, tile, buf, red); break;
       case 64: tile_body<64, T, W, MODE>(a, cd, td.curve, td.j0, tile, buf, red); break;
       default:
@@ -113,7 +116,8 @@ template <typename T, int W, int NX>
 constexpr bool tile_fits() {
   constexpr int KM = (NX - 1) / 3 + 1;
   constexpr int R = 64 * W / lanes_per_row<NX, T>();
-  return ((R + 2) * KM + 2) * int(sizeof(cplx<T>)) <= 160 * 1024;
+  return ((R + 2) * KM + 2) * int(sizeof(cplx<T>)) + 64 * W * u_stash<NX, T>() * int(sizeof(T)) <=
+         160 * 1024;
 }
 
 #ifndef KSC_MIXED
@@ -156,9 +160,8 @@ static hipError_t launch_mw(int mode, int grid, size_t lds, hipStream_t s, const
     return hipErrorInvalidValue;
   } else {
   switch (mode) {
-    case MODE_J:
-      hipExtLaunchKernelGGL((mixed_kernel<T, W, MODE_J>), dim3(grid), dim3(64 * W), lds, s, e0, e1, 0, a);
-      break;
+    case MODE_J:  // J-only mixed batches launch per grid size (host)
+      return hipErrorInvalidValue;
     case MODE_GRAD:
       hipExtLaunchKernelGGL((mixed_kernel<T, W, MODE_GRAD>), dim3(grid), dim3(64 * W), lds, s, e0, e1, 0, a);
       break;

@@ -342,7 +342,11 @@ size_t lds_for(const ksc_problem* p, int W, int nx) {
   // 16 bytes past the block and end 16 bytes after that)
   if (p->odd()) return size_t(rows_per_tile(p, W, nx) + 2) * (modes_of(nx) - 1) * p->esize() + 32;
   const size_t cs = 2 * p->esize();
-  return (size_t(rows_per_tile(p, W, nx) + 2) * modes_of(nx) + 2) * cs;
+  // plus the samples of u that each lane parks in LDS between the passes
+  // (ksc::u_stash of the tile kernels)
+  const size_t stash = (p->esize() == 4) ? size_t(64 * W) * ksc::u_stash<128, float>() * 4 : 0;
+  const size_t park = (nx == 128 || nx == 256) ? stash : 0;
+  return (size_t(rows_per_tile(p, W, nx) + 2) * modes_of(nx) + 2) * cs + park;
 }
 // Largest staging buffer over the grid sizes of the problem (one launch may
 // serve several).
@@ -564,7 +568,11 @@ ksc_status launch_fused(ksc_problem* p, int mode, const void* in, void* out, con
     if (e != hipSuccess) return fail(KSC_ERR_HIP, std::string("launch: ") + hipGetErrorString(e));
     return KSC_OK;
   }
-  if (p->mixed_ok) {
+  // (the J-only evaluation of a mixed batch runs one launch per grid size: the
+  // single mixed J-only kernel of this build gave wrong costs on its N_x = 128
+  // tiles, while the gradient and step kernels of the same form agree with
+  // the oracle on every curve)
+  if (p->mixed_ok && mode != ksc::MODE_J) {
     const size_t lds = lds_max(p, W);
     hipError_t e = launch_mixed(a, W, mode, grid, lds, s, e_first, e_last);
     if (e != hipSuccess) return fail(KSC_ERR_HIP, std::string("launch: ") + hipGetErrorString(e));

@@ -251,6 +251,17 @@ __device__ __forceinline__ void flush_block(V* __restrict__ gout, const V* __res
   }
 }
 
+// Samples of the physical field u that a lane parks in LDS between the two
+// passes of the gradient (the rest stay in registers).  Only where pass 0's
+// FP64 transform work space would not fit next to the whole field: N_x = 128
+// with one FP32 row per lane, N_x = 256 with an FP32 row per lane pair (128
+// samples per lane either way).  The host adds lanes * u_stash * sizeof(T)
+// bytes to the staging buffer's LDS.
+template <int NX, typename T>
+constexpr int u_stash() {
+  return (sizeof(T) == 4 && (NX == 128 || NX == 256)) ? 64 : 0;
+}
+
 template <int NX, typename T, int W, int MODE>
 __device__ __forceinline__ void tile_body(const KernelArgs<T>& a, const CurveDev& cd, int c,
                                           int j0, int tile, cplx<T>* buf, double* red) {
@@ -278,12 +289,16 @@ __device__ __forceinline__ void tile_body(const KernelArgs<T>& a, const CurveDev
   const T x0i = rows[(t + 1) * KM].i;  // raw Im u_hat_0 (zeroed in the output)
   const T csj = interior ? a.cs[cd.row_off + jr] : T(0);
   const T q1s = T(cd.q1 * cd.q1);                  // q1^2:  q_k^2 = k^2 q1^2
-  const T qN1 = T(cd.q1 / (4.0 * NX));             // q1 / (4 N_x): S is 2 N_x N_hat
   const T qY1 = T(cd.q1 / (2.0 * NX));             // q1 / (2 N_x): Q_hat = r2c/(2 N_x)
+  constexpr int CH = 5;                            // modes per LDS read batch (15 reads)
+  constexpr int NCH = (KM + CH - 1) / CH;
 
-  // Two passes through one copy of the transform code:
-  //   pass 0: In = u_hat  -> u = c2r(u_hat), S = r2c(u * u)   -> residual
-  //   pass 1: In = (i q / (2 N_x)) r_hat -> rho = c2r(In), S = r2c(u * rho) = Q_hat
+  // ---- pass 0, in FP64 whatever the state dtype: u = c2r(u_hat), the
+  // nonlinear term S = r2c(u * u) = 2 N_x N_hat and the residual.  In FP32 the
+  // rounding of N_hat differs from row to row and the adjoint's d/ds below
+  // differences neighbouring residual rows with a weight that grows like N_s;
+  // FP64 here (the same issue rate as non-packed FP32 on this chip) keeps
+  // the FP32 gradient within 1e-5 of the exact one at every curve length.
   cplx<T> In[KM];
   sfor<KM>([&](auto Kk) {
     constexpr int k = Kk;
@@ -291,122 +306,131 @@ __device__ __forceinline__ void tile_body(const KernelArgs<T>& a, const CurveDev
     if (k == 0) v.i = T(0);
     In[k] = v;
   });
-  T u[NX];
-  cplx<T> S[KM];
-  constexpr int NPASS = (MODE == MODE_J) ? 1 : 2;
-  constexpr int CH = 5;                            // modes per LDS read batch (15 reads)
-  constexpr int NCH = (KM + CH - 1) / CH;
-#pragma clang loop unroll(disable)
-  for (int pass = 0; pass < NPASS; ++pass) {
-    {
-      T v[NX];
-      spec_to_phys<NX, KM, T>(In, v);
-      if constexpr (MODE == MODE_J) {  // the field is not needed again
-        sfor<NX>([&](auto Nn) {
-          constexpr int n = Nn;
-          v[n] = v[n] * v[n];
-        });
-      } else {
-        if (pass == 0) {
-          sfor<NX>([&](auto Nn) {
-            constexpr int n = Nn;
-            u[n] = v[n];
-          });
-        }
-        sfor<NX>([&](auto Nn) {
-          constexpr int n = Nn;
-          v[n] = u[n] * v[n];
-        });
-      }
-      phys_to_spec2<NX, KM, T>(v, S);
-    }
-    if (pass == 0) {
-      // r_hat = -g (u_{j+1} - u_{j-1}) / (2 dsigma) + A u_hat - (i q / 2) N_hat,  S = 2 N_x N_hat;
-      // the state rows are read from LDS in batches of CH modes (all reads of a
-      // batch issued before its arithmetic), keeping few values live.
-      T rowR0 = T(0), rowR = T(0), rowD0 = T(0), rowD = T(0);
-      cplx<T> R[KM];
-      // (the empty asm keeps the per-mode constants below from being hoisted out
-      // of the pass loop, where they would stay live across both transforms)
-      T q1s_r = q1s, qN1_r = qN1;
-      __asm__ volatile("" : "+v"(q1s_r), "+v"(qN1_r));
-      // two batches of LDS reads in flight: batch c+1 is issued before the
-      // arithmetic of batch c
-      cplx<T> xm[2][CH], x0[2][CH], xp[2][CH];
-      auto load = [&](auto Cc, auto Bb) {
-        constexpr int k0 = int(Cc) * CH;
-        sfor<CH>([&](auto Ii) {
-          constexpr int k = k0 + int(Ii);
-          if constexpr (k < KM) {
-            xm[Bb][Ii] = rows[t * KM + k];
-            x0[Bb][Ii] = rows[(t + 1) * KM + k];
-            xp[Bb][Ii] = rows[(t + 2) * KM + k];
-          }
-        });
-      };
-      load(std::integral_constant<int, 0>{}, std::integral_constant<int, 0>{});
-      sfor<NCH>([&](auto Cc) {
-        constexpr int k0 = int(Cc) * CH;
-        constexpr int B = int(Cc) % 2;
-        if constexpr (int(Cc) + 1 < NCH)
-          load(std::integral_constant<int, int(Cc) + 1>{}, std::integral_constant<int, 1 - B>{});
-        __builtin_amdgcn_sched_barrier(0);
-        sfor<CH>([&](auto Ii) {
-          constexpr int i = Ii;
-          constexpr int k = k0 + i;
-          if constexpr (k < KM) {
-            const T dr = xp[B][i].r - xm[B][i].r;
-            T rr, ri;
-            if constexpr (k == 0) {
-              rr = -csj * dr;
-              ri = T(0);
-              rowR0 = rr * rr;
-              if constexpr (MODE == MODE_J) rowD0 = dr * dr;
-            } else {
-              const T di = xp[B][i].i - xm[B][i].i;
-              const T qn = T(k) * qN1_r;
-              const T q2 = T(k * k) * q1s_r;
-              const T Ak = fmaT(-q2, q2, q2);
-              rr = fmaT(-csj, dr, fmaT(Ak, x0[B][i].r, qn * S[k].i));
-              ri = fmaT(-csj, di, fmaT(Ak, x0[B][i].i, -qn * S[k].r));
-              rowR = fmaT(rr, rr, fmaT(ri, ri, rowR));
-              if constexpr (MODE == MODE_J) rowD = fmaT(dr, dr, fmaT(di, di, rowD));
-            }
-            R[k] = interior ? cplx<T>{rr, ri} : cplx<T>{T(0), T(0)};
-          }
-        });
-        // finish this batch's sums here (J-only mode has no other use of the
-        // residual, and sinking its arithmetic keeps every batch's reads live)
-        __asm__ volatile("" : "+v"(rowR0), "+v"(rowR), "+v"(rowD0), "+v"(rowD));
-        __builtin_amdgcn_sched_barrier(0);
+  // u: the first US samples in LDS after the staging buffer (sample n of
+  // lane t at ust[n * ROWS + t]: consecutive lanes, consecutive banks), the
+  // others in registers
+  constexpr int US = (MODE == MODE_J) ? 0 : u_stash<NX, T>();
+  T u[MODE == MODE_J ? 1 : NX - US];
+  T* __restrict__ ust = reinterpret_cast<T*>(buf + (BR * KM + E)) + t;
+  cplx<double> S0[KM];
+  {
+    double v[NX];
+    spec_to_phys<NX, KM, double, T>(In, v);
+    if constexpr (MODE != MODE_J) {
+      sfor<NX>([&](auto Nn) {
+        constexpr int n = Nn;
+        if constexpr (n < US)
+          ust[n * ROWS] = T(v[n]);
+        else
+          u[n - US] = T(v[n]);
       });
-      double pj = 0.0, pn = 0.0, pd = 0.0;
-      if (interior) {
-        const double rR = double(rowR0) + 2.0 * double(rowR);
-        pj = a.wlD[cd.row_off + jr] * rR;
-        if constexpr (MODE == MODE_J) {
-          const double rD = double(rowD0) + 2.0 * double(rowD);
-          pn = sqrt(rR * rD);
-          pd = sqrt(rD);
+    }
+    sfor<NX>([&](auto Nn) {
+      constexpr int n = Nn;
+      v[n] = v[n] * v[n];
+    });
+    phys_to_spec2<NX, KM, double>(v, S0);
+  }
+  cplx<T> R[KM];
+  {
+    // r_hat = -g (u_{j+1} - u_{j-1}) / (2 dsigma) + A u_hat - (i q / 2) N_hat in
+    // FP64 (the inputs are exact in it), rounded once to the state dtype; the
+    // state rows are read from LDS in batches of CH modes (all reads of a batch
+    // issued before its arithmetic), keeping few values live.
+    double rowR0 = 0.0, rowR = 0.0, rowD0 = 0.0, rowD = 0.0;
+    // (the empty asm keeps the per-mode constants below from being hoisted
+    // and kept live across the transforms)
+    double q1s_r = cd.q1 * cd.q1, qN1_r = cd.q1 / (4.0 * NX), cs_r = double(csj);
+    __asm__ volatile("" : "+v"(q1s_r), "+v"(qN1_r), "+v"(cs_r));
+    // two batches of LDS reads in flight: batch c+1 is issued before the
+    // arithmetic of batch c
+    cplx<T> xm[2][CH], x0[2][CH], xp[2][CH];
+    auto load = [&](auto Cc, auto Bb) {
+      constexpr int k0 = int(Cc) * CH;
+      sfor<CH>([&](auto Ii) {
+        constexpr int k = k0 + int(Ii);
+        if constexpr (k < KM) {
+          xm[Bb][Ii] = rows[t * KM + k];
+          x0[Bb][Ii] = rows[(t + 1) * KM + k];
+          xp[Bb][Ii] = rows[(t + 2) * KM + k];
         }
-      }
-      store_wave_partials<W, (MODE == MODE_J) ? 3 : 1>(pj, pn, pd, tile_partials(a, cd, c, tile, W));
-      if constexpr (MODE != MODE_J) {
-        // exchange residual rows through the staging buffer (outside rows read as 0)
-        __syncthreads();
-        T qY1_r = qY1;
-        __asm__ volatile("" : "+v"(qY1_r));
-        sfor<KM>([&](auto Kk) {
-          constexpr int k = Kk;
-          rows[(t + 1) * KM + k] = R[k];
-          const T qk = T(k) * qY1_r;
-          In[k] = cplx<T>{-qk * R[k].i, qk * R[k].r};
-        });
-        for (int i = t; i < 2 * KM; i += ROWS)
-          rows[(i < KM) ? i : (BR - 2) * KM + i] = cplx<T>{T(0), T(0)};
-        __syncthreads();
+      });
+    };
+    load(std::integral_constant<int, 0>{}, std::integral_constant<int, 0>{});
+    sfor<NCH>([&](auto Cc) {
+      constexpr int k0 = int(Cc) * CH;
+      constexpr int B = int(Cc) % 2;
+      if constexpr (int(Cc) + 1 < NCH)
+        load(std::integral_constant<int, int(Cc) + 1>{}, std::integral_constant<int, 1 - B>{});
+      __builtin_amdgcn_sched_barrier(0);
+      sfor<CH>([&](auto Ii) {
+        constexpr int i = Ii;
+        constexpr int k = k0 + i;
+        if constexpr (k < KM) {
+          const double dr = double(xp[B][i].r) - double(xm[B][i].r);
+          double rr, ri;
+          if constexpr (k == 0) {
+            rr = -cs_r * dr;
+            ri = 0.0;
+            rowR0 = rr * rr;
+            if constexpr (MODE == MODE_J) rowD0 = dr * dr;
+          } else {
+            const double di = double(xp[B][i].i) - double(xm[B][i].i);
+            const double qn = double(k) * qN1_r;
+            const double q2 = double(k * k) * q1s_r;
+            const double Ak = fmaT(-q2, q2, q2);
+            rr = fmaT(-cs_r, dr, fmaT(Ak, double(x0[B][i].r), qn * S0[k].i));
+            ri = fmaT(-cs_r, di, fmaT(Ak, double(x0[B][i].i), -qn * S0[k].r));
+            rowR = fmaT(rr, rr, fmaT(ri, ri, rowR));
+            if constexpr (MODE == MODE_J) rowD = fmaT(dr, dr, fmaT(di, di, rowD));
+          }
+          R[k] = interior ? cplx<T>{T(rr), T(ri)} : cplx<T>{T(0), T(0)};
+        }
+      });
+      // finish this batch's sums here (J-only mode has no other use of the
+      // residual, and sinking its arithmetic keeps every batch's reads live)
+      __asm__ volatile("" : "+v"(rowR0), "+v"(rowR), "+v"(rowD0), "+v"(rowD));
+      __builtin_amdgcn_sched_barrier(0);
+    });
+    double pj = 0.0, pn = 0.0, pd = 0.0;
+    if (interior) {
+      const double rR = rowR0 + 2.0 * rowR;
+      pj = a.wlD[cd.row_off + jr] * rR;
+      if constexpr (MODE == MODE_J) {
+        const double rD = rowD0 + 2.0 * rowD;
+        pn = sqrt(rR * rD);
+        pd = sqrt(rD);
       }
     }
+    store_wave_partials<W, (MODE == MODE_J) ? 3 : 1>(pj, pn, pd, tile_partials(a, cd, c, tile, W));
+  }
+  cplx<T> S[KM];
+  if constexpr (MODE != MODE_J) {
+    // exchange residual rows through the staging buffer (outside rows read as 0)
+    __syncthreads();
+    T qY1_r = qY1;
+    __asm__ volatile("" : "+v"(qY1_r));
+    sfor<KM>([&](auto Kk) {
+      constexpr int k = Kk;
+      rows[(t + 1) * KM + k] = R[k];
+      const T qk = T(k) * qY1_r;
+      In[k] = cplx<T>{-qk * R[k].i, qk * R[k].r};
+    });
+    for (int i = t; i < 2 * KM; i += ROWS)
+      rows[(i < KM) ? i : (BR - 2) * KM + i] = cplx<T>{T(0), T(0)};
+    __syncthreads();
+    // ---- pass 1, in the state dtype: rho = c2r(i q r_hat / (2 N_x)),
+    // S = r2c(u * rho) = Q_hat ----
+    T v[NX];
+    spec_to_phys<NX, KM, T>(In, v);
+    sfor<NX>([&](auto Nn) {
+      constexpr int n = Nn;
+      if constexpr (n < US)
+        v[n] = ust[n * ROWS] * v[n];
+      else
+        v[n] = u[n - US] * v[n];
+    });
+    phys_to_spec2<NX, KM, T>(v, S);
   }
 
   if constexpr (MODE != MODE_J) {
@@ -530,131 +554,138 @@ __device__ __forceinline__ void tile_body2(const KernelArgs<T>& a, const CurveDe
   const T x0i = rows[(t + 1) * KM].i;  // raw Im u_hat_0 (lane 0 uses it)
   const T csj = interior ? a.cs[cd.row_off + jr] : T(0);
   const T q1 = T(cd.q1);
-  const T qN1 = T(cd.q1 / (4.0 * NX));
   const T qY1 = T(cd.q1 / (2.0 * NX));
+  constexpr int CH = 7;
+  constexpr int NCH = (KH + CH - 1) / CH;
 
+  // ---- pass 0 in FP64 whatever the state dtype (see tile_body) ----
   cplx<T> In[KH];
   sfor<KH>([&](auto Ii) {
     constexpr int i = Ii;
     In[i] = ok(i) ? rows[(t + 1) * KM + 2 * i + p] : cplx<T>{T(0), T(0)};
   });
-  T u[NH];
-  cplx<T> S[KH];
-  constexpr int NPASS = (MODE == MODE_J) ? 1 : 2;
-  constexpr int CH = 7;
-  constexpr int NCH = (KH + CH - 1) / CH;
-#pragma clang loop unroll(disable)
-  for (int pass = 0; pass < NPASS; ++pass) {
-    {
-      T v[NH];
-      spec_to_phys_pair<NX, KH, T>(In, pf, v);
-      if constexpr (MODE == MODE_J) {  // the field is not needed again
-        sfor<NH>([&](auto Nn) {
-          constexpr int n = Nn;
-          v[n] = v[n] * v[n];
-        });
-      } else {
-        if (pass == 0) {
-          sfor<NH>([&](auto Nn) {
-            constexpr int n = Nn;
-            u[n] = v[n];
-          });
-        }
-        sfor<NH>([&](auto Nn) {
-          constexpr int n = Nn;
-          v[n] = u[n] * v[n];
-        });
-      }
-      phys_to_spec2_pair<NX, KH, T>(v, pf, S);
-    }
-    if (pass == 0) {
-      T rowR0 = T(0), rowR = T(0), rowD0 = T(0), rowD = T(0);
-      cplx<T> R[KH];
-      T q1_r = q1, qN1_r = qN1, pf_r = pf;
-      __asm__ volatile("" : "+v"(q1_r), "+v"(qN1_r), "+v"(pf_r));
-      sfor<NCH>([&](auto Cc) {
-        constexpr int i0 = int(Cc) * CH;
-        cplx<T> xm[CH], x0[CH], xp[CH];
-        sfor<CH>([&](auto Ii) {
-          constexpr int i = i0 + int(Ii);
-          if constexpr (i < KH) {
-            const int k = 2 * i + p;
-            const bool v = ok(i);
-            xm[Ii] = v ? rows[t * KM + k] : cplx<T>{T(0), T(0)};
-            x0[Ii] = v ? rows[(t + 1) * KM + k] : cplx<T>{T(0), T(0)};
-            xp[Ii] = v ? rows[(t + 2) * KM + k] : cplx<T>{T(0), T(0)};
-          }
-        });
-        __builtin_amdgcn_sched_barrier(0);
-        sfor<CH>([&](auto Ii) {
-          constexpr int ii = Ii;
-          constexpr int i = i0 + ii;
-          if constexpr (i < KH) {
-            const T kf = T(2 * i) + pf_r;           // mode number k = 2i + p
-            const T qn = kf * qN1_r;
-            const T qk = kf * q1_r;
-            const T q2 = qk * qk;
-            const T Ak = fmaT(-q2, q2, q2);
-            const T dr = xp[ii].r - xm[ii].r, di = xp[ii].i - xm[ii].i;
-            T rr = fmaT(-csj, dr, fmaT(Ak, x0[ii].r, qn * S[i].i));
-            T ri = fmaT(-csj, di, fmaT(Ak, x0[ii].i, -qn * S[i].r));
-            if constexpr (i == KH - 1) {
-              // past K on lane 1 when K+1 is odd: the transform still produced
-              // a coefficient there, which must not enter the cost or the adjoint
-              rr = ok(i) ? rr : T(0);
-              ri = ok(i) ? ri : T(0);
-            }
-            if constexpr (i == 0) {
-              // lane 0 entry 0 is mode 0: real, weight 1 in the Parseval sum
-              ri = odd ? ri : T(0);
-              const T e = fmaT(rr, rr, ri * ri);
-              rowR0 = odd ? T(0) : e;
-              rowR = odd ? e : T(0);
-              if constexpr (MODE == MODE_J) {
-                const T d = odd ? fmaT(dr, dr, di * di) : dr * dr;
-                rowD0 = odd ? T(0) : d;
-                rowD = odd ? d : T(0);
-              }
-            } else {
-              rowR = fmaT(rr, rr, fmaT(ri, ri, rowR));
-              if constexpr (MODE == MODE_J) rowD = fmaT(dr, dr, fmaT(di, di, rowD));
-            }
-            R[i] = interior ? cplx<T>{rr, ri} : cplx<T>{T(0), T(0)};
-          }
-        });
-        // finish this batch's sums here (J-only mode has no other use of the
-        // residual, and sinking its arithmetic keeps every batch's reads live)
-        __asm__ volatile("" : "+v"(rowR0), "+v"(rowR), "+v"(rowD0), "+v"(rowD));
-        __builtin_amdgcn_sched_barrier(0);
+  constexpr int US = (MODE == MODE_J) ? 0 : u_stash<NX, T>();
+  T u[MODE == MODE_J ? 1 : NH - US];
+  T* __restrict__ ust = reinterpret_cast<T*>(buf + (BR * KM + E)) + threadIdx.x;  // [US][NT]
+  cplx<double> S0[KH];
+  {
+    double v[NH];
+    spec_to_phys_pair<NX, KH, double, T>(In, double(p), v);
+    if constexpr (MODE != MODE_J) {
+      sfor<NH>([&](auto Nn) {
+        constexpr int n = Nn;
+        if constexpr (n < US)
+          ust[n * NT] = T(v[n]);
+        else
+          u[n - US] = T(v[n]);
       });
-      double pj = 0.0, pn = 0.0, pd = 0.0;
-      if (interior) {
-        // each lane holds its share of the row sums; J_arc needs whole rows
-        const double rR = double(rowR0) + 2.0 * double(rowR);
-        pj = a.wlD[cd.row_off + jr] * rR;
-        if constexpr (MODE == MODE_J) {
-          const double rD = double(rowD0) + 2.0 * double(rowD);
-          const double rRrow = rR + pair_swap(rR), rDrow = rD + pair_swap(rD);
-          pn = odd ? 0.0 : sqrt(rRrow * rDrow);
-          pd = odd ? 0.0 : sqrt(rDrow);
+    }
+    sfor<NH>([&](auto Nn) {
+      constexpr int n = Nn;
+      v[n] = v[n] * v[n];
+    });
+    phys_to_spec2_pair<NX, KH, double>(v, double(p), S0);
+  }
+  cplx<T> R[KH];
+  {
+    double rowR0 = 0.0, rowR = 0.0, rowD0 = 0.0, rowD = 0.0;
+    double q1_r = cd.q1, qN1_r = cd.q1 / (4.0 * NX), pf_r = double(p), cs_r = double(csj);
+    __asm__ volatile("" : "+v"(q1_r), "+v"(qN1_r), "+v"(pf_r), "+v"(cs_r));
+    sfor<NCH>([&](auto Cc) {
+      constexpr int i0 = int(Cc) * CH;
+      cplx<T> xm[CH], x0[CH], xp[CH];
+      sfor<CH>([&](auto Ii) {
+        constexpr int i = i0 + int(Ii);
+        if constexpr (i < KH) {
+          const int k = 2 * i + p;
+          const bool v = ok(i);
+          xm[Ii] = v ? rows[t * KM + k] : cplx<T>{T(0), T(0)};
+          x0[Ii] = v ? rows[(t + 1) * KM + k] : cplx<T>{T(0), T(0)};
+          xp[Ii] = v ? rows[(t + 2) * KM + k] : cplx<T>{T(0), T(0)};
         }
-      }
-      store_wave_partials<W, (MODE == MODE_J) ? 3 : 1>(pj, pn, pd, tile_partials(a, cd, c, tile, W));
-      if constexpr (MODE != MODE_J) {
-        __syncthreads();
-        T qY1_r = qY1, pf_y = pf;
-        __asm__ volatile("" : "+v"(qY1_r), "+v"(pf_y));
-        sfor<KH>([&](auto Ii) {
-          constexpr int i = Ii;
-          if (ok(i)) rows[(t + 1) * KM + 2 * i + p] = R[i];
-          const T qk = (T(2 * i) + pf_y) * qY1_r;
-          In[i] = cplx<T>{-qk * R[i].i, qk * R[i].r};
-        });
-        for (int i = threadIdx.x; i < 2 * KM; i += NT)
-          rows[(i < KM) ? i : (BR - 2) * KM + i] = cplx<T>{T(0), T(0)};
-        __syncthreads();
+      });
+      __builtin_amdgcn_sched_barrier(0);
+      sfor<CH>([&](auto Ii) {
+        constexpr int ii = Ii;
+        constexpr int i = i0 + ii;
+        if constexpr (i < KH) {
+          const double kf = double(2 * i) + pf_r;  // mode number k = 2i + p
+          const double qn = kf * qN1_r;
+          const double qk = kf * q1_r;
+          const double q2 = qk * qk;
+          const double Ak = fmaT(-q2, q2, q2);
+          const double dr = double(xp[ii].r) - double(xm[ii].r);
+          const double di = double(xp[ii].i) - double(xm[ii].i);
+          double rr = fmaT(-cs_r, dr, fmaT(Ak, double(x0[ii].r), qn * S0[i].i));
+          double ri = fmaT(-cs_r, di, fmaT(Ak, double(x0[ii].i), -qn * S0[i].r));
+          if constexpr (i == KH - 1) {
+            // past K on lane 1 when K+1 is odd: the transform still produced
+            // a coefficient there, which must not enter the cost or the adjoint
+            rr = ok(i) ? rr : 0.0;
+            ri = ok(i) ? ri : 0.0;
+          }
+          if constexpr (i == 0) {
+            // lane 0 entry 0 is mode 0: real, weight 1 in the Parseval sum
+            ri = odd ? ri : 0.0;
+            const double e = fmaT(rr, rr, ri * ri);
+            rowR0 = odd ? 0.0 : e;
+            rowR = odd ? e : 0.0;
+            if constexpr (MODE == MODE_J) {
+              const double d = odd ? fmaT(dr, dr, di * di) : dr * dr;
+              rowD0 = odd ? 0.0 : d;
+              rowD = odd ? d : 0.0;
+            }
+          } else {
+            rowR = fmaT(rr, rr, fmaT(ri, ri, rowR));
+            if constexpr (MODE == MODE_J) rowD = fmaT(dr, dr, fmaT(di, di, rowD));
+          }
+          R[i] = interior ? cplx<T>{T(rr), T(ri)} : cplx<T>{T(0), T(0)};
+        }
+      });
+      // finish this batch's sums here (J-only mode has no other use of the
+      // residual, and sinking its arithmetic keeps every batch's reads live)
+      __asm__ volatile("" : "+v"(rowR0), "+v"(rowR), "+v"(rowD0), "+v"(rowD));
+      __builtin_amdgcn_sched_barrier(0);
+    });
+    double pj = 0.0, pn = 0.0, pd = 0.0;
+    if (interior) {
+      // each lane holds its share of the row sums; J_arc needs whole rows
+      const double rR = rowR0 + 2.0 * rowR;
+      pj = a.wlD[cd.row_off + jr] * rR;
+      if constexpr (MODE == MODE_J) {
+        const double rD = rowD0 + 2.0 * rowD;
+        const double rRrow = rR + pair_swap(rR), rDrow = rD + pair_swap(rD);
+        pn = odd ? 0.0 : sqrt(rRrow * rDrow);
+        pd = odd ? 0.0 : sqrt(rDrow);
       }
     }
+    store_wave_partials<W, (MODE == MODE_J) ? 3 : 1>(pj, pn, pd, tile_partials(a, cd, c, tile, W));
+  }
+  cplx<T> S[KH];
+  if constexpr (MODE != MODE_J) {
+    __syncthreads();
+    T qY1_r = qY1, pf_y = pf;
+    __asm__ volatile("" : "+v"(qY1_r), "+v"(pf_y));
+    sfor<KH>([&](auto Ii) {
+      constexpr int i = Ii;
+      if (ok(i)) rows[(t + 1) * KM + 2 * i + p] = R[i];
+      const T qk = (T(2 * i) + pf_y) * qY1_r;
+      In[i] = cplx<T>{-qk * R[i].i, qk * R[i].r};
+    });
+    for (int i = threadIdx.x; i < 2 * KM; i += NT)
+      rows[(i < KM) ? i : (BR - 2) * KM + i] = cplx<T>{T(0), T(0)};
+    __syncthreads();
+    // ---- pass 1 in the state dtype: S = r2c(u * c2r(i q r_hat / (2 N_x))) ----
+    T v[NH];
+    spec_to_phys_pair<NX, KH, T>(In, pf, v);
+    sfor<NH>([&](auto Nn) {
+      constexpr int n = Nn;
+      if constexpr (n < US)
+        v[n] = ust[n * NT] * v[n];
+      else
+        v[n] = u[n - US] * v[n];
+    });
+    phys_to_spec2_pair<NX, KH, T>(v, pf, S);
   }
 
   if constexpr (MODE != MODE_J) {

@@ -49,3 +49,31 @@ def directional_rel_err(c: oracle.Curve, G_test: np.ndarray, G_ref: np.ndarray, 
         mag = float(np.sum(np.abs(G_ref.real * V.real) + np.abs(G_ref.imag * V.imag)))
         worst = max(worst, abs(dtest - dref) / mag)
     return worst
+
+
+def elementwise_rel_err(c: oracle.Curve, G_test: np.ndarray, G_ref: np.ndarray) -> float:
+    """max over rows j and modes k of |Pi_k (L2 gradient_test - L2 gradient_ref)_{jk}|
+    relative to max |Pi_k L2 gradient_ref|, Pi_k = 1/(1 + A_k^2): every element of
+    the gradient, in the same mode weighting as precond_rel_err."""
+    Pi = 1.0 / (1.0 + c.A ** 2)
+    a = l2_gradient(c, G_test) * Pi[None, :]
+    b = l2_gradient(c, G_ref) * Pi[None, :]
+    return float(np.abs(a - b).max() / np.abs(b).max())
+
+
+def oracle_descent(c: oracle.Curve, U: np.ndarray, n: int, dtau: float, storage=None,
+                   trace_every: int = 0):
+    """n steps of oracle.step from U.  With storage = np.float32 the state is
+    rounded to FP32 after every step (what an FP32 state holds between steps;
+    each step is still computed in FP64).  With trace_every > 0 also returns
+    the cost of the state entering every step i with (i + 1) % trace_every == 0
+    (the last step of each captured group, whose cost ksc_descend traces)."""
+    X = U.copy()
+    tr = []
+    for i in range(n):
+        if trace_every and (i + 1) % trace_every == 0:
+            tr.append(oracle.J2(c, X))
+        X = oracle.step(c, X, dtau)
+        if storage is not None:
+            X = ksinputs.round_to(X, storage)
+    return (X, tr) if trace_every else X

@@ -63,5 +63,6 @@ def test_cost_invariant_and_gradient_equivariant(dtype, ds):
     def rel(Gt, Gr):
         return np.linalg.norm((Gt - Gr) * P) / np.linalg.norm(Gr * P)
 
-    assert rel(G1, _translate(G0, q, a)) <= 10 * tol
-    assert rel(G2, _invert(G0)) <= 10 * tol
+    # each side is within tol of the exact gradient of its own input
+    assert rel(G1, _translate(G0, q, a)) <= 2 * tol
+    assert rel(G2, _invert(G0)) <= 2 * tol

@@ -5,7 +5,8 @@ import pytest
 
 import ksinputs
 import oracle
-from helpers import directional_rel_err, oracle_curve, precond_rel_err, seeded_state
+from helpers import (directional_rel_err, elementwise_rel_err, oracle_curve, oracle_descent,
+                     precond_rel_err, seeded_state)
 
 torch = pytest.importorskip("torch")
 
@@ -106,15 +107,17 @@ def test_J2_and_gradient_parity(dtype, case, waves):
     assert abs(J2.item() - J2_ref) <= tol * J2_ref
     assert abs(J2g.item() - J2_ref) <= tol * J2_ref
     Ja_ref = oracle.J_arc(c, U)
-    assert abs(Jarc.item() - Ja_ref) <= 10 * tol * Ja_ref
+    assert abs(Jarc.item() - Ja_ref) <= tol * Ja_ref
     Gg = prob.download(G, 0)
     Gr = oracle.grad(c, U)
     assert np.all(Gg[0] == 0) and np.all(Gg[-1] == 0)
     assert np.all(Gg[:, 0].imag == 0)
     e_pre = precond_rel_err(c, Gg, Gr)
     e_dir = directional_rel_err(c, Gg, Gr, [(7, i) for i in range(16)])
+    e_el = elementwise_rel_err(c, Gg, Gr)
     assert e_pre <= tol, e_pre
     assert e_dir <= tol, e_dir
+    assert e_el <= tol, e_el
 
 
 FULL = [(16, 300), (32, 300), (64, 300), (128, 300), (256, 300)]
@@ -152,10 +155,11 @@ def test_full_spectrum_parity(dtype, n_x, n_s, waves):
     assert abs(J2.item() - J2_ref) <= tol * J2_ref
     assert abs(J2g.item() - J2_ref) <= tol * J2_ref
     Ja_ref = oracle.J_arc(c, U)
-    assert abs(Jarc.item() - Ja_ref) <= 10 * tol * Ja_ref
+    assert abs(Jarc.item() - Ja_ref) <= tol * Ja_ref
     Gg = prob.download(G, 0)
     Gr = oracle.grad(c, U)
     assert precond_rel_err(c, Gg, Gr) <= tol
+    assert elementwise_rel_err(c, Gg, Gr) <= tol
     assert directional_rel_err(c, Gg, Gr, [(8, i) for i in range(8)]) <= tol
     got = prob.download(Y, 0)
     ref = oracle.step(c, U, 1e-4)
@@ -179,6 +183,8 @@ def test_step_parity(dtype, n_s, n_x):
     assert np.array_equal(got[0], U[0]) and np.array_equal(got[-1], U[-1])
     err = np.linalg.norm(got - ref) / np.linalg.norm(ref)
     assert err <= TOL[dtype], err
+    # every element of the state after the step
+    assert np.abs(got - ref).max() <= TOL[dtype] * np.abs(ref).max()
 
 
 @pytest.mark.parametrize("dtype", [np.float64, np.float32])
@@ -210,23 +216,71 @@ def test_descend_matches_oracle_and_single_steps(dtype):
         assert abs(trc[g] - ref) <= 4 * TOL[dtype] * ref
 
 
-@pytest.mark.parametrize("dtype,n_curves", [(np.float32, 12), (np.float64, 6)])
+@pytest.mark.parametrize("dtype,n_curves", [(np.float32, 256), (np.float64, 24)])
 def test_batched_uneven_curves_match_oracle(dtype, n_curves):
     """One launch over curves of different n_x, n_s and L (the mixed kernel;
-    in FP64 its N_x = 128 tiles use two lanes per row)."""
+    in FP64 its N_x = 128 tiles use two lanes per row): in FP32 every curve of
+    the 256-curve uneven workload (N_s up to 2048), in FP64 the first 24 - the
+    cost, J_arc, the gradient (norm, directions, every element) and one step,
+    under both launch policies."""
     specs = ksinputs.config_specs(3, n_curves=n_curves)
     tol = TOL[dtype]
+    dtau = 1e-3
     for policy in (0, 2):
+        print(f"uneven batch dtype={dtype.__name__} curves={n_curves} policy={policy}", flush=True)
         prob = _problem(specs, dtype, policy=policy)
         X, Us = _load(prob, specs, dtype)
-        J2 = prob.eval_J(X).cpu().numpy()
-        G, _ = prob.eval_grad(X)
+        J2, Ja = prob.eval_J(X, arc=True)
+        G, J2g = prob.eval_grad(X)
+        Y = torch.empty_like(X)
+        prob.step(X, Y, dtau)
+        torch.cuda.synchronize()
+        J2, Ja, J2g = J2.cpu().numpy(), Ja.cpu().numpy(), J2g.cpu().numpy()
+        worst = {}
         for i, (s, U) in enumerate(zip(specs, Us)):
             c = oracle_curve(s)
             ref = oracle.J2(c, U)
-            assert abs(J2[i] - ref) <= tol * ref
-            e = precond_rel_err(c, prob.download(G, i), oracle.grad(c, U))
-            assert e <= tol, (i, e)
+            Gg, Gr = prob.download(G, i), oracle.grad(c, U)
+            St, Sr = prob.download(Y, i), oracle.step(c, U, dtau)
+            errs = {
+                "J2": abs(J2[i] - ref) / ref, "J2_grad": abs(J2g[i] - ref) / ref,
+                "J_arc": abs(Ja[i] - oracle.J_arc(c, U)) / oracle.J_arc(c, U),
+                "pre": precond_rel_err(c, Gg, Gr), "elem": elementwise_rel_err(c, Gg, Gr),
+                "dir": directional_rel_err(c, Gg, Gr, [(7, k) for k in range(4)]),
+                "step": np.abs(St - Sr).max() / np.abs(Sr).max(),
+            }
+            for k, v in errs.items():
+                if v > worst.get(k, (0.0,))[0]:
+                    worst[k] = (v, i, s.n_s, s.n_x)
+            assert max(errs.values()) <= tol, (i, s, errs)
+        print("  worst per metric (error, curve, n_s, n_x):", worst, flush=True)
+
+
+def test_uneven_batch_graph_descent_matches_oracle_steps():
+    """The captured-graph descent (ksc_descend) of an uneven batch against the
+    oracle's steps, curve by curve: 100 steps in graphs of 10, J^2 traced
+    after every graph; the FP32 state is compared with the oracle run whose
+    state is rounded to FP32 after every step (what an FP32 state holds)."""
+    specs = ksinputs.config_specs(3, n_curves=256)
+    # both ends of the length range and every grid size
+    pick = sorted({min(range(256), key=lambda i: specs[i].n_s),
+                   max(range(256), key=lambda i: specs[i].n_s)} |
+                  {next(i for i in range(256) if specs[i].n_x == nx) for nx in (32, 64, 128)})
+    sub = [specs[i] for i in pick]
+    prob = _problem(sub, np.float32)
+    X, Us = _load(prob, sub, np.float32)
+    n, every, dtau = 100, 10, 1e-3
+    tr = prob.descend(X, n, dtau, every=every).cpu().numpy()
+    for i, (s, U) in enumerate(zip(sub, Us)):
+        c = oracle_curve(s)
+        ref, jr = oracle_descent(c, U, n, dtau, storage=np.float32, trace_every=every)
+        got = prob.download(X, i)
+        err = np.abs(got - ref).max() / np.abs(ref).max()
+        print(f"curve {pick[i]} n_s={s.n_s} n_x={s.n_x}: state error after {n} steps {err:.2e}",
+              flush=True)
+        assert err <= 1e-5, err
+        # the trace holds the cost of the state the last step of each graph started from
+        assert np.all(np.abs(tr[:, i] - jr) <= 1e-5 * np.array(jr)), (tr[:, i], jr)
 
 
 def test_plain_policy_matches_batched_bitwise():
@@ -257,25 +311,34 @@ def test_deterministic():
 
 
 def test_config2_full_size_parity():
-    """The large single curve (L=100, N_x=256, N_s=8192) against the oracle.
-
-    FP32 rounding of the transformed nonlinear term differs from row to row and
-    the adjoint's d/ds differences neighbouring rows with weight ~ N_s, so the
-    preconditioned gradient error of any FP32 evaluation grows like ~5e-9 N_s
-    (an FP32 emulation on the CPU gives 3.1e-6, 1.0e-5, 4.0e-5 at N_s = 512,
-    2048, 8192).  Gate: 1e-8 N_s, which is the 1e-5 target at N_s = 1024."""
+    """The large single curve (L=100, N_x=256, N_s=8192) against the oracle:
+    the cost, J_arc, the gradient (norm, directions, every element) and one
+    step, all at the FP32 tolerance."""
     spec = ksinputs.config_specs(2)[0]
     prob = _problem([spec], np.float32)
     X, (U,) = _load(prob, [spec], np.float32)
     c = oracle_curve(spec)
-    J2 = prob.eval_J(X).item()
+    J2, Ja = prob.eval_J(X, arc=True)
     G, _ = prob.eval_grad(X)
+    Y = torch.empty_like(X)
+    prob.step(X, Y, 1e-4)
+    torch.cuda.synchronize()
     ref = oracle.J2(c, U)
-    assert abs(J2 - ref) <= 1e-5 * ref
+    assert abs(J2.item() - ref) <= 1e-5 * ref
+    assert abs(Ja.item() - oracle.J_arc(c, U)) <= 1e-5 * oracle.J_arc(c, U)
     Gg = prob.download(G, 0)
     Gr = oracle.grad(c, U)
-    assert precond_rel_err(c, Gg, Gr) <= 1e-8 * spec.n_s
-    assert directional_rel_err(c, Gg, Gr, [(8, i) for i in range(16)]) <= 1e-5
+    e = (precond_rel_err(c, Gg, Gr), elementwise_rel_err(c, Gg, Gr),
+         directional_rel_err(c, Gg, Gr, [(8, i) for i in range(16)]))
+    print("workload 2 gradient errors (preconditioned, element-wise, directional):", e, flush=True)
+    assert e[0] <= 1e-5 and e[2] <= 1e-5, e
+    # element-wise: the adjoint differences residual rows that the lane-pair
+    # kernel exchanges rounded to FP32; at N_s = 8192 one element of the
+    # weighted gradient is off by 1.2e-5 of the largest (an FP32 emulation of
+    # the same arithmetic on the CPU gives the same figure)
+    assert e[1] <= 2e-5, e
+    St, Sr = prob.download(Y, 0), oracle.step(c, U, 1e-4)
+    assert np.abs(St - Sr).max() <= 1e-5 * np.abs(Sr).max()
 
 
 def test_flags_nonfinite_isolated_per_curve():
