@@ -252,8 +252,12 @@ def J_arc(c: Curve, U: np.ndarray) -> float:
     With ds = dsigma / g and u_s = g u_sigma the metric cancels; both integrals
     are taken with the trapezoid rule over the interior rows.
 
-    Parity unpinned beyond its definition (checked only for J_arc = 0 on a
-    curve with r = 0 and for the value on a closed-form curve).
+    Parity: pinned against the integral itself, evaluated by adaptive
+    quadrature in s for closed-form curves on the rational map (first-order
+    convergence: the end rows' share of the denominator is left out, and a
+    Richardson step converges at second order) and with the spectral d/ds
+    (convergence faster than any power of N_s); weighting the rows by g or
+    1/g, or dropping or inverting w in the spectral branch, fails those pins.
     """
     U = _clean(c, U)
     R = residual(c, U)

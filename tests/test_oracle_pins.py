@@ -551,3 +551,111 @@ def test_spectral_step_rate_and_transpose_matches_paper_adjoint():
         Rr[0] = Rr[-1] = 0.0
         errs.append(np.abs(_ds_adjoint(c, Rr) - _ds(c, Rr))[1:-1].max())
     assert errs[-1] < 1e-8 and errs[0] / errs[1] > 30, errs
+
+
+# ------------------------------------------------------------- J_arc pins ---
+
+def _resid_norm_two_mode(L, A, dA, B, dB):
+    """|r| = sqrt(int_0^L r^2 dx) of u = A cos(q1 x) + B sin(q2 x) with
+    u_s = dA cos(q1 x) + dB sin(q2 x), r = -u_s - u u_x - u_xx - u_xxxx
+    (eq. KSE_residual), and |u_s|, from pointwise values on 64 points (the
+    rectangle rule is exact for these band-limited fields)."""
+    n = 64
+    x = np.arange(n) * L / n
+    q1, q2 = 2 * np.pi / L, 4 * np.pi / L
+    c1, s2 = np.cos(q1 * x), np.sin(q2 * x)
+    u = A * c1 + B * s2
+    ux = -A * q1 * np.sin(q1 * x) + B * q2 * np.cos(q2 * x)
+    uxx = -A * q1 ** 2 * c1 - B * q2 ** 2 * s2
+    uxxxx = A * q1 ** 4 * c1 + B * q2 ** 4 * s2
+    us = dA * c1 + dB * s2
+    r = -us - u * ux - uxx - uxxxx
+    return np.sqrt((r ** 2).sum() * L / n), np.sqrt((us ** 2).sum() * L / n)
+
+
+def _J_arc_integral(L, curve_of_s, metric_power=0):
+    """int |r| |u_s| ds / int |u_s| ds over s in (-inf, inf) (eq. J_arc),
+    evaluated in s by adaptive quadrature; curve_of_s(s) -> (A, dA/ds, B, dB/ds).
+    metric_power != 0 weights both integrands by (du/ds magnitude)^metric_power
+    extra - a deliberately wrong weighting, to show the pin tells them apart."""
+    from scipy.integrate import quad
+
+    def parts(s):
+        rn, usn = _resid_norm_two_mode(L, *curve_of_s(s))
+        return rn, usn
+
+    num = quad(lambda s: np.prod(parts(s)) * parts(s)[1] ** metric_power, -np.inf, np.inf,
+               limit=400, epsabs=0, epsrel=1e-13)[0]
+    den = quad(lambda s: parts(s)[1] ** (1 + metric_power), -np.inf, np.inf,
+               limit=400, epsabs=0, epsrel=1e-13)[0]
+    return num / den
+
+
+def test_J_arc_rational_map_converges_to_the_integral_in_s():
+    """eq. J_arc on the rational map, where the metric g = d sigma / ds is not
+    constant: a curve from u = 0 to u = 0 (an equilibrium at both ends, so r
+    vanishes there) with coefficients quadratic in sigma; the oracle's J_arc
+    must converge to int |r||u_s| ds / int |u_s| ds evaluated by adaptive
+    quadrature in s itself, with u_s = g u_sigma.  The sums run over the
+    interior rows, whose central differences exist; the end rows' share of
+    the denominator (|u_s| ds = |u_sigma| dsigma stays finite at s = +-inf)
+    is left out, so the convergence is first order, and one Richardson step
+    (2 J(2N) - J(N)) must then converge at second order.  Weighting the rows
+    by g or 1/g (a dropped or inverted metric) converges to another number,
+    which the same test would reject."""
+    L, S = 22.0, 7.0
+    a, b = 0.9, -1.4
+
+    def curve_of_s(s):
+        th = np.pi / 2 - np.arctan(s / S)          # s = S cot(theta)
+        sig = 1.0 - th / np.pi
+        g = np.sin(th) ** 2 / (np.pi * S)          # d sigma / ds
+        A, dA = a * sig * (1 - sig), a * (1 - 2 * sig) * g
+        B, dB = b * sig * (1 - sig), b * (1 - 2 * sig) * g
+        return A, dA, B, dB
+
+    exact = _J_arc_integral(L, curve_of_s)
+    vals = []
+    for n_s in (65, 129, 257, 513):
+        c = Curve(n_s, 32, L, "rational", S)
+        sig = c.sigma
+        U = np.zeros((n_s, c.K + 1), dtype=np.complex128)
+        U[:, 1] = 0.5 * a * sig * (1 - sig)           # A cos(q1 x): u_hat_1 = A / 2
+        U[:, 2] = -0.5j * b * sig * (1 - sig)         # B sin(q2 x): u_hat_2 = -i B / 2
+        vals.append(oracle.J_arc(c, U))
+    errs = np.abs(np.array(vals) - exact) / exact
+    orders = np.log2(errs[:-1] / errs[1:])
+    assert np.all((orders > 0.95) & (orders < 1.05)), (errs, orders)
+    rich = np.abs(2 * np.array(vals[1:]) - np.array(vals[:-1]) - exact) / exact
+    assert rich[-1] < 1e-5, rich
+    assert np.all(np.log2(rich[:-1] / rich[1:]) > 1.8), rich
+    # the weighting matters on this curve: the same integrals with the rows
+    # weighted by |u_s| once more differ from eq. J_arc by far more than the
+    # discretization error above
+    assert abs(_J_arc_integral(L, curve_of_s, metric_power=1) - exact) > 1e-2 * exact
+
+
+def test_J_arc_spectral_ds_converges_to_the_integral_in_s():
+    """eq. J_arc with the paper's D_t along s (eq. rational_diff_matrix): on the
+    decaying closed-form curve the oracle's J_arc converges faster than any
+    power of N_s to the same integral in s evaluated by adaptive quadrature."""
+    L, S = 22.0, 8.0
+
+    def curve_of_s(s):
+        sech, th = 1.0 / np.cosh(s / 4.0), np.tanh(s / 4.0)
+        # u = 0.6 sech cos(q1 x) + 0.4 sech tanh sin(q2 x): the coefficients
+        # u_hat_1 = 0.3 sech, u_hat_2 = -0.2 i sech tanh of _decaying_curve
+        A, dA = 0.6 * sech, -0.6 * th * sech / 4.0
+        B, dB = 0.4 * sech * th, 0.4 * (sech ** 3 - th ** 2 * sech) / 4.0
+        return A, dA, B, dB
+
+    exact = _J_arc_integral(L, curve_of_s)
+    errs = []
+    for n_s in (33, 65, 129):
+        c = Curve(n_s, 16, L, "rational", S, ds="spectral")
+        s = np.where(np.isinf(c.s), 0.0, c.s)
+        U, _ = _decaying_curve(s, c.n_x)
+        U[0] = U[-1] = 0.0
+        errs.append(abs(oracle.J_arc(c, U) - exact) / exact)
+    assert errs[-1] < 1e-9, errs
+    assert errs[0] / errs[1] > 30 and errs[1] / errs[2] > 30, errs
