@@ -238,6 +238,21 @@ ksc_status ksc_descend(ksc_problem* p, void* state, void* scratch, int64_t n_ste
 ksc_status ksc_set_scheme(ksc_problem* p, int32_t scheme);
 ksc_status ksc_get_scheme(const ksc_problem* p, int32_t* scheme);
 
+/* Heavy-ball momentum (Polyak) of later ksc_descend calls under
+ * KSC_SCHEME_IMPLICIT_S (an extension, not in the paper): every step writes
+ *     u_{n+1} = u_n + delta_n + beta (u_n - u_{n-1})
+ * on the interior rows (delta_n the implicit-in-s increment of u_n), which
+ * shortens the slow final approach along the smallest eigenvalues of the
+ * descent flow.  A curve whose cost J2(u_n) rose against J2(u_{n-1}) takes
+ * that step without the momentum term (an adaptive restart), so the cost can
+ * rise only by single steps.
+ * Every ksc_descend call starts from rest (u_{-1} = u_0); `every` must be
+ * even while beta > 0 (KSC_ERR_ARG), and ksc_descend under the paper's scheme
+ * with beta > 0 returns KSC_ERR_UNSUPPORTED.  ksc_step ignores it.
+ * beta in [0, 1) (KSC_ERR_ARG otherwise); 0 (the default) turns it off. */
+ksc_status ksc_set_momentum(ksc_problem* p, double beta);
+ksc_status ksc_get_momentum(const ksc_problem* p, double* beta);
+
 /* Choose the launch shape (waves per tile, persistent or not) by timing the
  * candidates on scratch buffers; the choice is cached in the JSON file at
  * cache_path (nullable: no file) keyed by device, ROCm version and problem

@@ -17,7 +17,8 @@ and u_hat_0 = 0.  Draw order per curve: a(B), b(B), [a(A), b(A)], a(p), b(p),
 from ``numpy.random.default_rng(SeedSequence([config, curve]))``.
 
 Initial curve: u_j = (1 - sigma_j) A + sigma_j B + sin(pi sigma_j) p with
-sigma_j = j / (n_s - 1).
+sigma_j = j / (n_s - 1); for workload 4 the blend is replaced by samples of
+a stored KS trajectory from A to B (config4_curves).
 """
 from __future__ import annotations
 
@@ -35,6 +36,7 @@ __all__ = [
     "round_to",
     "random_direction",
     "config4_curves",
+    "interpolate_samples",
 ]
 
 
@@ -126,8 +128,9 @@ def config_specs(cfg: int, n_curves: int | None = None) -> list[CurveSpec]:
        perturbation 0.3, FP32.
     3: 256 curves of uneven shape, N_x in {32,64,128}, N_s in [128, 2048],
        L in {22,39,66}, each seeded as workload 0.
-    4: 64 curves, L=66, N_x=128, N_s=1024, finite map T=20 (endpoints come
-       from a stored trajectory file; this spec gives the shape only).
+    4: 64 curves, L=66, N_x=128, N_s=1024, finite map T=20 (the curves are
+       stored KS trajectory pieces plus a seeded perturbation, config4_curves;
+       this spec gives the shape only).
     """
     if cfg == 0:
         return [CurveSpec(64, 32, 22.0, 4, 1.0, 4, 0.1, False, (0, 0))]
@@ -281,27 +284,53 @@ def random_direction(seed, n_s: int, n_modes: int, kmax: int = 8) -> np.ndarray:
     return v
 
 
-C4_ENDPOINTS = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))),
-                            "tests", "golden", "c4_endpoints.npz")
+C4_TRAJECTORIES = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))),
+                               "tests", "golden", "c4_trajectories.npz")
+
+
+def interpolate_samples(samples: np.ndarray, t_new: np.ndarray, order: int = 6) -> np.ndarray:
+    """Values at t_new in [0, 1] of uniformly spaced samples (axis 0 at t =
+    m / (M - 1)) by local Lagrange interpolation through the `order` nearest
+    samples (degree order - 1; windows are clamped at the ends).  Exact at the
+    sample points."""
+    M = samples.shape[0]
+    x = np.asarray(t_new, dtype=np.float64) * (M - 1)
+    start = np.clip(np.floor(x).astype(int) - (order // 2 - 1), 0, M - order)
+    out = np.zeros((len(x),) + samples.shape[1:], dtype=np.result_type(samples, np.complex128))
+    for a in range(order):
+        w = np.ones(len(x))
+        for b in range(order):
+            if b != a:
+                w *= (x - (start + b)) / (a - b)
+        out += w.reshape((-1,) + (1,) * (samples.ndim - 1)) * samples[start + a]
+    return out
 
 
 def config4_curves(n_curves: int = 64, n_s: int = 1024, replicas: int = 1):
-    """Workload 4: stored trajectory endpoints (A_i, B_i = Phi_20(A_i)) with the
-    blend-plus-perturbation interior, perturbation smooth(4, 0.1) seeded (4, i).
-    replicas > 1 repeats the batch (used to stream more than the caches hold).
+    """Workload 4 (finite map s = T sigma, T = 20): curve i starts as the
+    stored KS trajectory piece from A_i to B_i = Phi_T(A_i), sampled at
+    s_j = T sigma_j (interpolated to the n_s rows from its 129 stored
+    samples), plus the perturbation sin(pi sigma) smooth(4, 0.1) seeded
+    (4, i, 1); the end rows are A_i and B_i exactly.  replicas > 1 repeats
+    the batch (used to stream more than the caches hold).
     Returns (specs, list of U_hat [n_s, 43])."""
-    d = np.load(C4_ENDPOINTS)
-    A, B = d["A"], d["B"]
+    d = np.load(C4_TRAJECTORIES)
+    traj = d["traj"]
     specs, Us = [], []
     base = config_specs(4, n_curves)
+    sig = np.arange(n_s, dtype=np.float64) / (n_s - 1)
     for r in range(replicas):
         for i in range(n_curves):
             sp = base[i]
             if n_s != sp.n_s:
                 sp = CurveSpec(n_s, sp.n_x, sp.L, sp.kmax_end, sp.amp_end, sp.kmax_pert,
                                sp.amp_pert, sp.random_A, sp.seed, sp.map, sp.scale, sp.s0)
+            tr = traj[i % traj.shape[0]].astype(np.complex128)
             rng = np.random.default_rng(np.random.SeedSequence([4, i, 1]))
-            p = smooth_coeffs(rng, 4, 0.1, A.shape[1])
+            p = smooth_coeffs(rng, 4, 0.1, tr.shape[1])
+            U = interpolate_samples(tr, sig) + np.sin(np.pi * sig)[:, None] * p[None, :]
+            U[0], U[-1] = tr[0], tr[-1]
+            U[:, 0] = U[:, 0].real
             specs.append(sp)
-            Us.append(blend_curve(A[i % A.shape[0]], B[i % B.shape[0]], p, n_s))
+            Us.append(U)
     return specs, Us

@@ -37,6 +37,7 @@ from .ks import (  # noqa: F401
     implicit_s_operator,
     step_implicit_s,
     step_implicit_s_odd,
+    descend_implicit_s_momentum,
     from_physical_curve,
     to_physical_curve,
 )

@@ -502,3 +502,34 @@ def step_implicit_s_odd(c: Curve, B: np.ndarray, dtau: float) -> np.ndarray:
     """``step_implicit_s`` of the inversion-symmetric curve b (B_k is real and
     acts per mode, so the step stays in the subspace)."""
     return full_to_odd(step_implicit_s(c, odd_to_full(B), dtau))
+
+
+def descend_implicit_s_momentum(c: Curve, U: np.ndarray, n: int, dtau: float, beta: float,
+                                storage=None) -> np.ndarray:
+    """n implicit-in-s steps with heavy-ball momentum (Polyak's two-step
+    iteration; an acceleration beyond the paper's scheme):
+
+        u_{i+1} = step_implicit_s(u_i) + beta (u_i - u_{i-1}),  u_{-1} = u_0,
+
+    the momentum term on the interior rows only (end rows fixed, Im of mode 0
+    zero), and dropped for a step whose input cost rose against the previous
+    input's, J^2(u_i) > J^2(u_{i-1}) (1 + 1e-12) (an adaptive restart).
+    storage = np.float32 rounds each new state to FP32 (what an FP32 state
+    holds between steps).
+
+    Parity: with beta = 0 it is n steps of ``step_implicit_s``; the momentum
+    term and the restart are the definitions above.
+    """
+    prev = _clean(c, U)
+    cur = prev.copy()
+    J_prev = np.nan
+    for _ in range(n):
+        J_cur = J2(c, cur)
+        nxt = step_implicit_s(c, cur, dtau)
+        if not (np.isfinite(J_prev) and J_cur > J_prev * (1.0 + 1e-12)):
+            nxt[1:-1] += beta * (cur[1:-1] - prev[1:-1])
+        nxt[:, 0] = nxt[:, 0].real
+        if storage is not None and np.dtype(storage) == np.float32:
+            nxt = nxt.astype(np.complex64).astype(np.complex128)
+        prev, cur, J_prev = cur, nxt, J_cur
+    return cur

@@ -27,7 +27,8 @@ EXPORTED = (
     "ksc_phys_numel", "ksc_phys_offset", "ksc_n_modes", "ksc_set_endpoints",
     "ksc_phys_to_spec", "ksc_spec_to_phys", "ksc_eval_J", "ksc_eval_grad", "ksc_step",
     "ksc_descend", "ksc_tune", "ksc_set_launch", "ksc_get_launch", "ksc_query_flags",
-    "ksc_set_timing", "ksc_read_timing", "ksc_set_scheme", "ksc_get_scheme", "ksc_last_error",
+    "ksc_set_timing", "ksc_read_timing", "ksc_set_scheme", "ksc_get_scheme", "ksc_set_momentum",
+    "ksc_get_momentum", "ksc_last_error",
 )
 
 
@@ -95,6 +96,8 @@ def lib() -> ctypes.CDLL:
         "ksc_get_launch": (i32, [vp, ctypes.POINTER(i32), ctypes.POINTER(i32)]),
         "ksc_set_scheme": (i32, [vp, i32]),
         "ksc_get_scheme": (i32, [vp, ctypes.POINTER(i32)]),
+        "ksc_set_momentum": (i32, [vp, dbl]),
+        "ksc_get_momentum": (i32, [vp, ctypes.POINTER(dbl)]),
         "ksc_query_flags": (i32, [vp, ctypes.POINTER(ctypes.c_uint32)]),
         "ksc_set_timing": (i32, [vp, i32]),
         "ksc_read_timing": (i32, [vp, ctypes.POINTER(dbl), ctypes.POINTER(dbl),

@@ -85,6 +85,7 @@ struct PostArgs {
   double* Jarc;          // nullable
   double* prevJ2;
   unsigned* flags;
+  unsigned char* rose;   // with track: 1 where the cost rose against the previous evaluation
   const unsigned char* active;
   int track;
   int fin_blocks;        // blocks [0, fin_blocks): one wave per curve reduces its cost
@@ -151,7 +152,9 @@ __global__ __launch_bounds__(256) void post_kernel(PostArgs<T> a) {
     if (!finite_bits(s0)) f |= KSC_FLAG_NONFINITE;
     if (a.track) {
       const double pv = a.prevJ2[c];
-      if (finite_bits(pv) && pv >= 0 && s0 > pv * (1.0 + 1e-12) + 1e-300) f |= KSC_FLAG_INCREASED;
+      const bool up = finite_bits(pv) && pv >= 0 && s0 > pv * (1.0 + 1e-12) + 1e-300;
+      if (up) f |= KSC_FLAG_INCREASED;
+      a.rose[c] = up ? 1 : 0;
       a.prevJ2[c] = s0;
     }
     if (f) a.flags[c] |= f;
@@ -257,6 +260,7 @@ struct ksc_problem {
   long long part_slots = 0;   // allocated partial slots (3 doubles each)
   double* d_prevJ2 = nullptr;
   unsigned* d_flags = nullptr;
+  unsigned char* d_rose = nullptr;  // per curve: the last tracked cost rose (momentum restart)
   double* d_J2 = nullptr;
   int part_cap = 0;
   double pre_dtau = std::nan("");
@@ -286,6 +290,7 @@ struct ksc_problem {
   // descent scheme (ksc_set_scheme); the implicit-in-s step keeps the
   // gradient in d_G and walks the solve table d_simp
   int scheme = KSC_SCHEME_PAPER;
+  double momentum = 0.0;  // heavy-ball momentum of the implicit-in-s descent (ksc_set_momentum)
   void* d_G = nullptr;
   ksc::SimpBlock* d_simp = nullptr;
   int n_simp = 0;
@@ -302,6 +307,7 @@ struct ksc_problem {
     int every = 0;
     const void* active = nullptr;
     int W = 0, policy = 0;
+    double momentum = 0;
     hipStream_t stream = nullptr;
   } gkey;
 
@@ -613,6 +619,7 @@ ksc_status launch_post(ksc_problem* p, int mode, const void* in, void* out, cons
   a.Jarc = Jarc;
   a.prevJ2 = p->d_prevJ2;
   a.flags = p->d_flags;
+  a.rose = p->d_rose;
   a.active = active;
   a.track = track;
   const int b = 256;
@@ -1000,7 +1007,7 @@ ksc_status build_simp(ksc_problem* p) {
 }
 
 template <typename T>
-ksc_status launch_simp_t(ksc_problem* p, const void* in, void* out, double dtau,
+ksc_status launch_simp_t(ksc_problem* p, const void* in, void* out, double dtau, double beta,
                          const uint8_t* active, hipStream_t s) {
   ksc::SimpArgs<T> a{};
   a.in = static_cast<const T*>(in);
@@ -1013,6 +1020,8 @@ ksc_status launch_simp_t(ksc_problem* p, const void* in, void* out, double dtau,
   a.blocks = p->d_simp;
   a.active = active;
   a.dtau = T(dtau);
+  a.beta = T(beta);
+  a.rose = p->d_rose;
   a.odd = p->odd() ? 1 : 0;
   hipError_t e;
   if constexpr (sizeof(T) == 8)
@@ -1023,16 +1032,17 @@ ksc_status launch_simp_t(ksc_problem* p, const void* in, void* out, double dtau,
   return KSC_OK;
 }
 
-// One descent step in -> out under the problem's scheme.
-ksc_status step_once(ksc_problem* p, const void* in, void* out, double dtau,
+// One descent step in -> out under the problem's scheme; beta > 0 (the
+// implicit-in-s scheme only) adds beta (in - out on entry).
+ksc_status step_once(ksc_problem* p, const void* in, void* out, double dtau, double beta,
                      const uint8_t* active, double* J2, int track, bool finalize, hipStream_t s) {
   if (p->scheme == KSC_SCHEME_PAPER)
     return run(p, ksc::MODE_STEP, in, out, nullptr, active, J2, nullptr, track, finalize, s);
   ksc_status st = run(p, ksc::MODE_GRAD, in, p->d_G, nullptr, active, J2, nullptr, track,
                       finalize, s);
   if (st != KSC_OK) return st;
-  return p->dtype == KSC_F64 ? launch_simp_t<double>(p, in, out, dtau, active, s)
-                             : launch_simp_t<float>(p, in, out, dtau, active, s);
+  return p->dtype == KSC_F64 ? launch_simp_t<double>(p, in, out, dtau, beta, active, s)
+                             : launch_simp_t<float>(p, in, out, dtau, beta, active, s);
 }
 
 template <typename T>
@@ -1203,9 +1213,11 @@ ksc_status ksc_create_opts(const ksc_curve_desc* descs, int32_t n_curves, const 
   if (hipMalloc(&p->d_cd, n_curves * sizeof(CurveDev)) != hipSuccess ||
       hipMalloc(&p->d_prevJ2, n_curves * sizeof(double)) != hipSuccess ||
       hipMalloc(&p->d_J2, n_curves * sizeof(double)) != hipSuccess ||
-      hipMalloc(&p->d_flags, n_curves * sizeof(unsigned)) != hipSuccess)
+      hipMalloc(&p->d_flags, n_curves * sizeof(unsigned)) != hipSuccess ||
+      hipMalloc(&p->d_rose, n_curves) != hipSuccess)
     return cleanup(fail(KSC_ERR_HIP, "ksc_create: workspace allocation failed"));
-  if (hipMemset(p->d_flags, 0, n_curves * sizeof(unsigned)) != hipSuccess)
+  if (hipMemset(p->d_flags, 0, n_curves * sizeof(unsigned)) != hipSuccess ||
+      hipMemset(p->d_rose, 0, n_curves) != hipSuccess)
     return cleanup(fail(KSC_ERR_HIP, "ksc_create: hipMemset failed"));
   {
     std::vector<double> nanv(n_curves, std::nan(""));
@@ -1230,7 +1242,7 @@ ksc_status ksc_destroy(ksc_problem* p) {
   for (hipEvent_t e : p->tev) hipEventDestroy(e);
   void* bufs[] = {p->d_bounds, p->d_cd,  p->d_tiles, p->d_cs,    p->d_wlT,    p->d_wlD,
                   p->d_A,   p->d_pre,   p->d_sqrtL, p->d_part,   p->d_prevJ2,
-                  p->d_flags, p->d_J2,  p->d_edge,  p->d_dpool,  p->d_spec,  p->d_Y,
+                  p->d_flags, p->d_rose, p->d_J2,  p->d_edge,  p->d_dpool,  p->d_spec,  p->d_Y,
                   p->d_WR,  p->d_P,   p->d_sgroups, p->d_kpart, p->d_G, p->d_simp};
   for (void* b : bufs)
     if (b) hipFree(b);
@@ -1329,7 +1341,7 @@ ksc_status ksc_step(ksc_problem* p, const void* in, void* out, double dtau, doub
   if (!(dtau > 0) || !std::isfinite(dtau)) return fail(KSC_ERR_ARG, "ksc_step: dtau must be > 0");
   ksc_status st = ensure_pre(p, dtau, p->stream);
   if (st != KSC_OK) return st;
-  return step_once(p, in, out, dtau, nullptr, J2, 0, J2 != nullptr, p->stream);
+  return step_once(p, in, out, dtau, 0.0, nullptr, J2, 0, J2 != nullptr, p->stream);
 }
 
 // Record `every` steps (state -> scratch -> state ...) plus per-step
@@ -1343,7 +1355,7 @@ static ksc_status capture_descent(ksc_problem* p, void* state, void* scratch, do
   for (int i = 0; i < every && st == KSC_OK; ++i) {
     const void* in = (i % 2 == 0) ? state : scratch;
     void* out = (i % 2 == 0) ? scratch : state;
-    st = step_once(p, in, out, dtau, active, p->d_J2, 1, true, s);
+    st = step_once(p, in, out, dtau, p->momentum, active, p->d_J2, 1, true, s);
   }
   hipGraph_t g = nullptr;
   hipError_t e = hipStreamEndCapture(s, &g);
@@ -1358,7 +1370,8 @@ static ksc_status capture_descent(ksc_problem* p, void* state, void* scratch, do
     drop_graph(p);
     return fail(KSC_ERR_HIP, std::string("instantiate: ") + hipGetErrorString(e));
   }
-  p->gkey = ksc_problem::Key{state, scratch, dtau, every, active, p->W, p->policy, p->stream};
+  p->gkey = ksc_problem::Key{state, scratch, dtau, every, active, p->W, p->policy, p->momentum,
+                             p->stream};
   return KSC_OK;
 }
 
@@ -1369,6 +1382,10 @@ ksc_status ksc_descend(ksc_problem* p, void* state, void* scratch, int64_t n_ste
   if (n_steps < 0) return fail(KSC_ERR_ARG, "ksc_descend: n_steps < 0");
   if (every < 1) return fail(KSC_ERR_ARG, "ksc_descend: every must be >= 1");
   if (!(dtau > 0) || !std::isfinite(dtau)) return fail(KSC_ERR_ARG, "ksc_descend: dtau must be > 0");
+  if (p->momentum > 0 && p->scheme != KSC_SCHEME_IMPLICIT_S)
+    return fail(KSC_ERR_UNSUPPORTED, "ksc_descend: momentum needs the implicit-in-s scheme");
+  if (p->momentum > 0 && every % 2 != 0)
+    return fail(KSC_ERR_ARG, "ksc_descend: momentum needs an even `every`");
   if (n_steps == 0) return KSC_OK;
   ksc_status st = ensure_pre(p, dtau, p->stream);
   if (st != KSC_OK) return st;
@@ -1376,11 +1393,12 @@ ksc_status ksc_descend(ksc_problem* p, void* state, void* scratch, int64_t n_ste
   KSC_HIP(hipMemcpyAsync(scratch, state, p->state_bytes(), hipMemcpyDeviceToDevice, p->stream));
   // groups of `every` steps; an odd group ends in scratch and is copied back
   const int G = every;
-  const ksc_problem::Key want{state, scratch, dtau, G, active, p->W, p->policy, p->stream};
+  const ksc_problem::Key want{state, scratch, dtau, G, active, p->W, p->policy, p->momentum,
+                              p->stream};
   const bool same = p->gexec && want.state == p->gkey.state && want.scratch == p->gkey.scratch &&
                     want.dtau == p->gkey.dtau && want.every == p->gkey.every &&
                     want.active == p->gkey.active && want.W == p->gkey.W &&
-                    want.policy == p->gkey.policy;
+                    want.policy == p->gkey.policy && want.momentum == p->gkey.momentum;
   if (!same) {
     // the capture stream must not run ahead of work already queued on p->stream
     KSC_HIP(hipStreamSynchronize(p->stream));
@@ -1400,7 +1418,7 @@ ksc_status ksc_descend(ksc_problem* p, void* state, void* scratch, int64_t n_ste
   for (int64_t i = 0; i < rem; ++i) {
     const void* in = (i % 2 == 0) ? state : scratch;
     void* out = (i % 2 == 0) ? scratch : state;
-    st = step_once(p, in, out, dtau, active, p->d_J2, 1, true, p->stream);
+    st = step_once(p, in, out, dtau, p->momentum, active, p->d_J2, 1, true, p->stream);
     if (st != KSC_OK) return st;
   }
   if (rem % 2 == 1)
@@ -1416,11 +1434,28 @@ ksc_status ksc_set_scheme(ksc_problem* p, int32_t scheme) {
     if (p->spectral())
       return fail(KSC_ERR_UNSUPPORTED,
                   "ksc_set_scheme: the implicit-in-s step needs the central-difference d/ds");
+    if (p->scheme == KSC_SCHEME_IMPLICIT_S && p->d_simp) return KSC_OK;  // already set up
+    // (a captured descent graph points at the solve table build_simp replaces)
+    drop_graph(p);
     ksc_status st = build_simp(p);
     if (st != KSC_OK) return st;
   }
   if (scheme != p->scheme) drop_graph(p);
   p->scheme = scheme;
+  return KSC_OK;
+}
+
+ksc_status ksc_set_momentum(ksc_problem* p, double beta) {
+  if (!p) return fail(KSC_ERR_ARG, "ksc_set_momentum: null problem");
+  if (!(beta >= 0.0 && beta < 1.0)) return fail(KSC_ERR_ARG, "ksc_set_momentum: beta must be in [0, 1)");
+  if (beta != p->momentum) drop_graph(p);
+  p->momentum = beta;
+  return KSC_OK;
+}
+
+ksc_status ksc_get_momentum(const ksc_problem* p, double* beta) {
+  if (!p || !beta) return fail(KSC_ERR_ARG, "ksc_get_momentum: null pointer");
+  *beta = p->momentum;
   return KSC_OK;
 }
 

@@ -40,6 +40,8 @@ struct SimpArgs {
   const SimpBlock* __restrict__ blocks;
   const uint8_t* __restrict__ active;  // nullable
   T dtau;
+  T beta;                          // heavy-ball momentum: out += beta (in - out on entry); 0: off
+  const uint8_t* __restrict__ rose;  // per curve: 1 restarts the momentum (the cost just rose)
   int odd;                         // rows of K reals (modes 1..K) instead of K+1 complex
 };
 

@@ -26,6 +26,14 @@
 // reduction in LDS; then every thread recovers its rows.  The right-hand side
 // -dtau L^dagger_k is the gradient G = 2 w_j L c_k L^dagger_k of the fused
 // kernel, rescaled per row.
+//
+// Optional heavy-ball momentum (Polyak): with beta > 0 the interior rows get
+// u_hat + delta + beta (u_hat - u_prev), u_prev being what the output buffer
+// holds on entry (in a ping-pong descent: the state one step before u_hat).
+// A curve whose cost rose at this step's evaluation drops the momentum term
+// for the step (a restart from rest, after O'Donoghue & Candes' adaptive
+// restart of accelerated gradient schemes), so the iteration cannot coast
+// away from the basin it is descending in.
 #include "ksc_launch_simp.hpp"
 
 namespace ksc {
@@ -296,9 +304,17 @@ __global__ __launch_bounds__(kSimpThreads) void simp_kernel(SimpArgs<T> a) {
         x = xin[i];
       else
         x = vin[ix];
+      V mom;
+#pragma unroll
+      for (int v = 0; v < NV; ++v) mom.v[v] = T(0);
+      if (a.beta != T(0) && !(a.rose != nullptr && a.rose[blk.curve] != 0)) {  // uniform per workgroup
+        const V prev = vout[ix];
+#pragma unroll
+        for (int v = 0; v < NV; ++v) mom.v[v] = a.beta * (x.v[v] - prev.v[v]);
+      }
 #pragma unroll
       for (int v = 0; v < NV; ++v)
-        x.v[v] += (i < mi) ? y[i][v] + l[i] * s_left[v] + r[i] * s_me[v] : s_me[v];
+        x.v[v] += ((i < mi) ? y[i][v] + l[i] * s_left[v] + r[i] * s_me[v] : s_me[v]) + mom.v[v];
       vout[ix] = clean(x);
     }
   }

@@ -84,12 +84,16 @@ class GpuBackend:
         p64 = Problem(self.prob.curves, dtype=self._torch.float64, device=self.state.device,
                       space=self.prob.space, ds=self.prob.ds)
         p64.set_scheme(self.prob.scheme)
+        p64.set_momentum(self.prob.momentum)
         b = GpuBackend(p64, self.state.double())
         b.active.copy_(self.active)
         return b
 
     def flags(self) -> np.ndarray:
         return self.prob.query_flags()
+
+    def set_momentum(self, beta: float) -> None:
+        self.prob.set_momentum(beta)
 
 
 def save_checkpoint(path: str, backend, log: DescentLog, active: np.ndarray) -> None:
@@ -113,10 +117,13 @@ def descend_to(backend, dtau: float, J_target: float = 1e-8, max_steps: int = 10
                stall_records: int = 10, fp64_finish: bool = True, Jarc_target: float | None = None,
                min_dtau: float = 1e-9, rise_tol: float = 1e-3, checkpoint: str | None = None,
                checkpoint_every: int | None = None, resume: bool = False, log: DescentLog | None = None,
-               progress=None):
+               progress=None, momentum: float = 0.0):
     """Run the descent; returns (backend, DescentLog).  The returned backend may
     be a promoted (FP64) one holding the final state.  progress(log, J) is
-    called after every accepted chunk with the per-curve J."""
+    called after every accepted chunk with the per-curve J.  momentum > 0
+    (implicit-in-s scheme) turns on the library's heavy-ball momentum from
+    the FP64 switch on, for the slow final approach; the FP32 phase, far from
+    the minimum, runs the plain steps."""
     every = max(1, int(every))
     chunk = int(chunk or every)
     chunk = max(every, (chunk // every) * every)
@@ -128,6 +135,8 @@ def descend_to(backend, dtau: float, J_target: float = 1e-8, max_steps: int = 10
         arr, active, log = load_checkpoint(checkpoint)
         if log.dtype == "f64" and backend.dtype != "f64":
             backend = backend.promote()
+            if momentum > 0:
+                backend.set_momentum(momentum)
         backend.restore(arr)
         dtau = log.dtau
     backend.set_active(active)
@@ -137,14 +146,18 @@ def descend_to(backend, dtau: float, J_target: float = 1e-8, max_steps: int = 10
     stall = np.zeros(nc, dtype=int)
     log.converged = J_prev < J_target
     since_ckpt = 0
+    momentum_on = bool(momentum > 0 and resume and log.dtype == "f64")
     while log.steps < max_steps:
         n = min(chunk, max_steps - log.steps)
         n = max(every, (n // every) * every)
         tr = backend.run(n, dtau, every)
         J2 = backend.J2()
         Jn = np.sqrt(np.abs(J2))
-        # a rise beyond rounding noise (rise_tol, relative) or a non-finite cost
-        rose = (~np.isfinite(J2)) | (np.isfinite(J_prev) & (Jn > J_prev * (1 + rise_tol)) & active)
+        # a rise beyond rounding noise (rise_tol, relative) or a non-finite cost;
+        # with momentum the cost is not monotone (the library restarts the
+        # momentum of a curve at each rise), so only a rise by half is rejected
+        tol = max(rise_tol, 0.5) if momentum_on else rise_tol
+        rose = (~np.isfinite(J2)) | (np.isfinite(J_prev) & (Jn > J_prev * (1 + tol)) & active)
         trace_bad = ~np.all(np.isfinite(tr[:, active]), axis=0) if tr.size else np.zeros(active.sum(), bool)
         if np.any(rose & active) or np.any(trace_bad):
             backend.restore(last_good)
@@ -185,6 +198,9 @@ def descend_to(backend, dtau: float, J_target: float = 1e-8, max_steps: int = 10
             if np.any(need):
                 backend = backend.promote()
                 backend.set_active(active)
+                if momentum > 0:
+                    backend.set_momentum(momentum)
+                    momentum_on = True
                 log.dtype = "f64"
                 log.events.append((log.steps, "switched to FP64"))
                 last_good = backend.snapshot()
@@ -199,7 +215,7 @@ def descend_to(backend, dtau: float, J_target: float = 1e-8, max_steps: int = 10
 
 
 def main(argv=None):
-    """Descend the batched workload-4 curves (stored KS-trajectory endpoints,
+    """Descend the batched workload-4 curves (stored KS-trajectory pieces,
     L = 66, N_x = 128) to a target J, FP32 first and FP64 to finish, printing
     one progress line per chunk.  With --connection, descend instead the
     initial curves of eq. KSE_initial_curve (a = 0) between stored L = 22
@@ -242,6 +258,9 @@ def main(argv=None):
     ap.add_argument("--scheme", default="paper", choices=["paper", "implicit_s"],
                     help="descent step: the paper's (A_k^2 implicit) or implicit_s (the whole "
                          "linear part, d/ds included, implicit: larger stable dtau)")
+    ap.add_argument("--momentum", type=float, default=0.0,
+                    help="heavy-ball momentum beta of the implicit_s descent from the FP64 switch "
+                         "on (0: off; include/ksc.h ksc_set_momentum)")
     ap.add_argument("--history", default=None,
                     help="write the J and J_arc records (per chunk) and the events to this JSON file")
     args = ap.parse_args(argv)
@@ -289,7 +308,8 @@ def main(argv=None):
     b = GpuBackend(prob, X)
     t0 = time.time()
     J0 = np.sqrt(b.J2())
-    print(f"start: {len(specs)} curves ({ds} d/ds, {space} space, {args.scheme} step), "
+    print(f"start: {len(specs)} curves ({ds} d/ds, {space} space, {args.scheme} step"
+          + (f", momentum {args.momentum}" if args.momentum else "") + "), "
           f"J max {J0.max():.3e} "
           f"min {J0.min():.3e}"
           + (f", J_arc {np.array2string(b.J_arc(), precision=3)}" if args.jarc_target else ""),
@@ -307,7 +327,7 @@ def main(argv=None):
                          every=args.every, chunk=args.chunk, switch_J=args.switch,
                          stall_records=args.stall_records, checkpoint=args.checkpoint,
                          checkpoint_every=args.checkpoint_every, resume=args.resume,
-                         progress=report, Jarc_target=args.jarc_target)
+                         progress=report, Jarc_target=args.jarc_target, momentum=args.momentum)
     J = np.sqrt(np.abs(b2.J2()))
     ok = J < args.target
     if args.jarc_target is not None:

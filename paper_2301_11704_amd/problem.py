@@ -245,6 +245,17 @@ class Problem:
             raise ValueError(f"unknown scheme {scheme!r}")
         check(lib().ksc_set_scheme(self._h, self.SCHEMES[scheme]))
 
+    def set_momentum(self, beta: float = 0.0):
+        """Heavy-ball momentum of later descend calls under the implicit_s
+        scheme (include/ksc.h, ksc_set_momentum); 0 turns it off."""
+        check(lib().ksc_set_momentum(self._h, float(beta)))
+
+    @property
+    def momentum(self) -> float:
+        v = ctypes.c_double()
+        check(lib().ksc_get_momentum(self._h, ctypes.byref(v)))
+        return float(v.value)
+
     @property
     def scheme(self) -> str:
         v = ctypes.c_int32()

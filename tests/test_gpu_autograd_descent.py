@@ -88,7 +88,7 @@ def test_autograd_path_workload_vs_fd_and_oracle():
 
 
 def test_workload4_fp64_matches_oracle():
-    """The FP64 finish evaluates the workload-4 batch (trajectory endpoints:
+    """The FP64 finish evaluates the workload-4 batch (trajectory pieces:
     every mode populated) like the oracle: J2 of 8 curves to 1e-12 and the
     gradient of 2 curves in the preconditioned norm."""
     specs, Us = ksinputs.config4_curves(64)

@@ -282,3 +282,39 @@ def test_driver_cli_runs_the_implicit_scheme(tmp_path, capsys):
     assert h["scheme"] == "implicit_s"
     J0, J1 = np.array(h["records"][0]["J"]), np.array(h["records"][-1]["J"])
     assert np.all(J1 < J0), (J0, J1)
+
+
+@pytest.mark.parametrize("dtype", [np.float64, np.float32])
+def test_momentum_descent_matches_oracle(dtype):
+    """ksc_descend with heavy-ball momentum (and its restart on a cost rise)
+    against the oracle's iteration, on three uneven curves: 40 steps in graphs
+    of 10; the FP32 run against the oracle run that rounds its state to FP32
+    after every step."""
+    import paper_2301_11704_amd as ksc
+    specs = [ksinputs.CurveSpec(n, nx, 22.0, 4, 1.0, 4, 0.1, False, (97, i))
+             for i, (n, nx) in enumerate([(64, 32), (91, 64), (40, 32)])]
+    tdt = torch.float64 if dtype == np.float64 else torch.float32
+    prob = ksc.Problem([ksc.CurveDesc(s.n_s, s.n_x, s.L) for s in specs], dtype=tdt)
+    prob.set_scheme("implicit_s")
+    prob.set_momentum(0.9)
+    X = prob.new_state()
+    Us = []
+    for c, s in enumerate(specs):
+        U = seeded_state(s, dtype)
+        prob.upload(X, c, U)
+        Us.append(U)
+    prob.descend(X, 40, 0.01, every=10)
+    tol = 1e-12 if dtype == np.float64 else 1e-5
+    for c, (s, U) in enumerate(zip(specs, Us)):
+        cur = oracle.Curve(s.n_s, s.n_x, s.L, s.map, s.scale)
+        ref = oracle.descend_implicit_s_momentum(cur, U, 40, 0.01, 0.9,
+                                                 storage=None if dtype == np.float64 else np.float32)
+        got = prob.download(X, c)
+        err = np.abs(got - ref).max() / np.abs(ref).max()
+        print(f"curve {c}: momentum descent error {err:.2e}", flush=True)
+        assert err <= tol
+    with pytest.raises(ksc.KscError):
+        prob.descend(X, 10, 0.01, every=5)  # momentum needs an even `every`
+    prob.set_scheme("paper")
+    with pytest.raises(ksc.KscError):
+        prob.descend(X, 10, 0.001, every=10)  # and the implicit-in-s scheme
