@@ -286,6 +286,23 @@ ksc_status ksc_set_timing(ksc_problem* p, int32_t enable);
  * Waits for the recorded events (blocks the host). */
 ksc_status ksc_read_timing(ksc_problem* p, double* fused_ms, double* post_ms, int64_t* n_evals);
 
+/* J2[c] of n_curves curves that share one descriptor, laid out as one
+ * state of such a problem (curve-major, n_s rows of K+1 complex values each;
+ * full space, central-difference d/ds), without a problem object and without
+ * allocating device memory: for callers that cannot allocate (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc).  The
+ * tables, tile list and per-wave partial sums live in one fixed array of
+ * KSC_NOALLOC_SCRATCH_BYTES per GPU inside the library (held until the
+ * process ends); a batch needing more returns KSC_ERR_SHAPE before any launch
+ * (8 MiB holds, e.g., 64 curves of 1024 rows).  Every call on a GPU reuses
+ * that GPU's array, so calls that overlap on one GPU (different streams or
+ * threads) race.  state: device input; J2: device output of n_curves doubles;
+ * hip_stream as for ksc_create.  Enqueued asynchronously; same kernels and
+ * tolerance as ksc_eval_J. */
+#define KSC_NOALLOC_SCRATCH_BYTES (8u << 20)
+ksc_status ksc_eval_J_noalloc(const ksc_curve_desc* desc, int32_t n_curves, int32_t dtype,
+                              const void* state, double* J2, void* hip_stream);
+
 /* Message of the last failed call on this thread ("" if none). */
 const char* ksc_last_error(void);
 

@@ -20,6 +20,7 @@ KSC_MAP_RATIONAL, KSC_MAP_FINITE = 0, 1
 KSC_FLAG_NONFINITE, KSC_FLAG_INCREASED = 1, 2
 KSC_LAUNCH_AUTO, KSC_LAUNCH_PLAIN, KSC_LAUNCH_PERSISTENT = 0, 1, 2
 KSC_SCHEME_PAPER, KSC_SCHEME_IMPLICIT_S = 0, 1
+KSC_NOALLOC_SCRATCH_BYTES = 8 << 20
 
 # Every symbol include/ksc.h declares.
 EXPORTED = (
@@ -28,7 +29,7 @@ EXPORTED = (
     "ksc_phys_to_spec", "ksc_spec_to_phys", "ksc_eval_J", "ksc_eval_grad", "ksc_step",
     "ksc_descend", "ksc_tune", "ksc_set_launch", "ksc_get_launch", "ksc_query_flags",
     "ksc_set_timing", "ksc_read_timing", "ksc_set_scheme", "ksc_get_scheme", "ksc_set_momentum",
-    "ksc_get_momentum", "ksc_last_error",
+    "ksc_get_momentum", "ksc_eval_J_noalloc", "ksc_last_error",
 )
 
 
@@ -102,6 +103,7 @@ def lib() -> ctypes.CDLL:
         "ksc_set_timing": (i32, [vp, i32]),
         "ksc_read_timing": (i32, [vp, ctypes.POINTER(dbl), ctypes.POINTER(dbl),
                                   ctypes.POINTER(i64)]),
+        "ksc_eval_J_noalloc": (i32, [ctypes.POINTER(CurveDescC), i32, i32, vp, vp, vp]),
         "ksc_last_error": (ctypes.c_char_p, []),
     }
     for name, (res, args) in sig.items():

@@ -9,6 +9,7 @@
 #include <cstdio>
 #include <cstring>
 #include <fstream>
+#include <mutex>
 #include <sstream>
 #include <string>
 #include <vector>
@@ -1054,6 +1055,183 @@ std::vector<T> cast_vec(const std::vector<double>& v) {
 
 // ------------------------------------------------------------------- C ABI --
 
+// ------------------------------------------------- allocation-free J^2 --
+//
+// ksc_eval_J_noalloc evaluates J^2 of curves that share one descriptor with
+// no problem object and no device allocation: the per-row metric tables, the
+// curve and tile lists and the per-wave partial sums live in `scratch`, one
+// fixed array per GPU (held until the process ends).  In host code the
+// array's name is only a stand-in; its device address comes from
+// hipGetSymbolAddress, once per device, and only that address is passed on.
+
+namespace {
+
+constexpr size_t kNoallocBytes = KSC_NOALLOC_SCRATCH_BYTES;
+static __device__ __align__(256) unsigned char scratch[kNoallocBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of this device's scratch array (looked up on first use).
+hipError_t scratch_address(void** out) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* ptr = nullptr;
+    e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    g_scratch_ptr[dev] = ptr;
+  }
+  *out = g_scratch_ptr[dev];
+  return hipSuccess;
+}
+
+// Byte offsets of the pieces inside the scratch array (256-byte aligned).
+struct NoallocLayout {
+  size_t curves, tiles, cs, wlT, wlD, part, end;
+};
+size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
+NoallocLayout noalloc_layout(int n_curves, int n_s, int n_tiles, int W, size_t es) {
+  NoallocLayout l{};
+  size_t o = 0;
+  l.curves = o; o = align256(o + size_t(n_curves) * sizeof(CurveDev));
+  l.tiles = o;  o = align256(o + size_t(n_tiles) * sizeof(TileDev));
+  l.cs = o;     o = align256(o + size_t(n_s) * es);
+  l.wlT = o;    o = align256(o + size_t(n_s) * es);
+  l.wlD = o;    o = align256(o + size_t(n_s) * 8);
+  l.part = o;   o = align256(o + size_t(n_tiles) * W * 3 * 8);
+  l.end = o;
+  return l;
+}
+
+// The same tables ksc_create builds on the host (FP64, cast to T), for one
+// descriptor shared by every curve: one thread per row, per curve, per tile.
+template <typename T>
+__global__ void noalloc_setup_kernel(ksc_curve_desc d, int n_curves, int rows_per_tile,
+                                     int tiles_per_curve, unsigned char* base, NoallocLayout l) {
+  CurveDev* cdv = reinterpret_cast<CurveDev*>(base + l.curves);
+  TileDev* tl = reinterpret_cast<TileDev*>(base + l.tiles);
+  T* cs = reinterpret_cast<T*>(base + l.cs);
+  T* wlT = reinterpret_cast<T*>(base + l.wlT);
+  double* wlD = reinterpret_cast<double*>(base + l.wlD);
+  const int km = (d.n_x - 1) / 3 + 1;
+  const long long n_tiles = (long long)n_curves * tiles_per_curve;
+  const long long total = d.n_s + n_curves + n_tiles;
+  const double dsig = 1.0 / (d.n_s - 1);
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < total;
+       i += (long long)gridDim.x * blockDim.x) {
+    if (i < d.n_s) {
+      const int j = int(i);
+      double g;
+      if (d.map == KSC_MAP_RATIONAL) {
+        const double sn = sin(M_PI * (1.0 - j * dsig));
+        g = sn * sn / (M_PI * d.scale);
+      } else {
+        g = 1.0 / d.scale;
+      }
+      const bool interior = (j > 0 && j < d.n_s - 1);
+      cs[j] = T(interior ? g / (2.0 * dsig) : 0.0);
+      wlT[j] = T(interior ? 2.0 * dsig / g * d.L : 0.0);
+      wlD[j] = interior ? dsig / g * d.L : 0.0;
+    } else if (i < d.n_s + n_curves) {
+      const int c = int(i - d.n_s);
+      CurveDev v{};
+      v.off = (long long)c * d.n_s * km;
+      v.poff = (long long)c * d.n_s * d.n_x;
+      v.n_s = d.n_s;
+      v.n_x = d.n_x;
+      v.km = km;
+      v.row_off = 0;  // every curve shares the row tables
+      v.mode_off = 0;
+      v.tile_begin = c * tiles_per_curve;
+      v.n_tiles = tiles_per_curve;
+      v.q1 = 2.0 * M_PI / d.L;
+      cdv[c] = v;
+    } else {
+      const long long t = i - d.n_s - n_curves;
+      tl[t] = TileDev{int(t / tiles_per_curve), int(t % tiles_per_curve) * rows_per_tile};
+    }
+  }
+}
+
+// J^2[c] = the curve's per-wave partials summed by one wave in a fixed order.
+__global__ __launch_bounds__(256) void noalloc_reduce_kernel(const double* part, int slots_per_curve,
+                                                             int n_curves, double* J2) {
+  const int c = blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (c >= n_curves) return;
+  double s = 0.0;
+  for (int t = lane; t < slots_per_curve; t += 64) s += part[3 * ((long long)c * slots_per_curve + t)];
+  s = wave_sum_fixed(s);
+  if (lane == 0) J2[c] = s;
+}
+
+template <typename T>
+ksc_status eval_J_noalloc_t(const ksc_curve_desc& d, int n_curves, const void* state, double* J2,
+                            hipStream_t s, void* base) {
+  const int lanes = (d.n_x * int(sizeof(T)) > 512) ? 2 : 1;
+  const int km = modes_of(d.n_x);
+  int dev = 0;
+  KSC_HIP(hipGetDevice(&dev));
+  int lds_dev = 0;
+  KSC_HIP(hipDeviceGetAttribute(&lds_dev, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
+  // the widest tile whose staging buffer (and parked u samples) fits in LDS,
+  // as for a problem object (lds_for)
+  int W = 0;
+  size_t lds = 0;
+  for (int w : {4, 2, 1}) {
+    const size_t rows = size_t(64 * w / lanes) + 2;
+    const size_t park = (sizeof(T) == 4 && (d.n_x == 128 || d.n_x == 256))
+                            ? size_t(64 * w) * ksc::u_stash<128, float>() * 4 : 0;
+    const size_t b = (rows * km + 2) * 2 * sizeof(T) + park;
+    if (b <= size_t(lds_dev)) {
+      W = w;
+      lds = b;
+      break;
+    }
+  }
+  if (W == 0) return fail(KSC_ERR_UNSUPPORTED, "ksc_eval_J_noalloc: tile does not fit in LDS");
+  const int R = 64 * W / lanes;
+  const int tpc = (d.n_s + R - 1) / R;
+  const long long n_tiles = (long long)tpc * n_curves;
+  if (n_tiles > (1ll << 30))
+    return fail(KSC_ERR_SHAPE, "ksc_eval_J_noalloc: too many tiles");
+  const NoallocLayout l = noalloc_layout(n_curves, d.n_s, int(n_tiles), W, sizeof(T));
+  if (l.end > kNoallocBytes)
+    return fail(KSC_ERR_SHAPE, "ksc_eval_J_noalloc: the batch needs " + std::to_string(l.end) +
+                                   " bytes of scratch, more than KSC_NOALLOC_SCRATCH_BYTES (" +
+                                   std::to_string(kNoallocBytes) + ")");
+  unsigned char* b = static_cast<unsigned char*>(base);
+  const long long items = d.n_s + n_curves + n_tiles;
+  const int sg = int(std::min<long long>((items + 255) / 256, 4096));
+  hipLaunchKernelGGL((noalloc_setup_kernel<T>), dim3(sg), dim3(256), 0, s, d, n_curves, R, tpc, b, l);
+  KSC_HIP(hipGetLastError());
+  KernelArgs<T> a{};
+  a.in = static_cast<const cplx<T>*>(state);
+  a.curves = reinterpret_cast<const CurveDev*>(b + l.curves);
+  a.tiles = reinterpret_cast<const TileDev*>(b + l.tiles);
+  a.cs = reinterpret_cast<const T*>(b + l.cs);
+  a.wlT = reinterpret_cast<const T*>(b + l.wlT);
+  a.wlD = reinterpret_cast<const double*>(b + l.wlD);
+  a.partials = reinterpret_cast<double*>(b + l.part);
+  a.part_stride = 0;  // slots in tile order: curve c owns tiles [c tpc, (c+1) tpc)
+  a.km_max = km;
+  a.n_tiles = int(n_tiles);
+  a.tile_base = 0;
+  hipError_t e = launch_uniform<T>(d.n_x, W, ksc::MODE_J, int(n_tiles), lds, s, a, nullptr, nullptr);
+  if (e != hipSuccess) return fail(KSC_ERR_HIP, std::string("launch: ") + hipGetErrorString(e));
+  hipLaunchKernelGGL(noalloc_reduce_kernel, dim3((n_curves + 3) / 4), dim3(256), 0, s,
+                     reinterpret_cast<const double*>(b + l.part), tpc * W, n_curves, J2);
+  KSC_HIP(hipGetLastError());
+  return KSC_OK;
+}
+
+}  // namespace
+
 extern "C" {
 
 const char* ksc_last_error(void) { return g_err.c_str(); }
@@ -1522,6 +1700,26 @@ ksc_status ksc_read_timing(ksc_problem* p, double* fused_ms, double* post_ms, in
   if (p->timing_overflow)
     return fail(KSC_ERR_STATE, "ksc_read_timing: more evaluations than the timing window holds");
   return KSC_OK;
+}
+
+ksc_status ksc_eval_J_noalloc(const ksc_curve_desc* desc, int32_t n_curves, int32_t dtype,
+                              const void* state, double* J2, void* hip_stream) {
+  if (!desc || !state || !J2) return fail(KSC_ERR_ARG, "ksc_eval_J_noalloc: null pointer");
+  if (n_curves < 1) return fail(KSC_ERR_ARG, "ksc_eval_J_noalloc: n_curves < 1");
+  if (dtype != KSC_F32 && dtype != KSC_F64) return fail(KSC_ERR_ARG, "ksc_eval_J_noalloc: bad dtype");
+  const ksc_curve_desc& d = *desc;
+  if (!nx_supported(d.n_x)) return fail(KSC_ERR_UNSUPPORTED, "ksc_eval_J_noalloc: n_x not in {8,...,256}");
+  if (d.n_s < 3 || d.n_s > (1 << 26)) return fail(KSC_ERR_SHAPE, "ksc_eval_J_noalloc: bad n_s");
+  if (!(d.L > 0) || !std::isfinite(d.L)) return fail(KSC_ERR_ARG, "ksc_eval_J_noalloc: L must be > 0");
+  if (d.map != KSC_MAP_RATIONAL && d.map != KSC_MAP_FINITE)
+    return fail(KSC_ERR_ARG, "ksc_eval_J_noalloc: bad map");
+  if (!(d.scale > 0) || !std::isfinite(d.scale))
+    return fail(KSC_ERR_ARG, "ksc_eval_J_noalloc: scale must be > 0");
+  void* base = nullptr;
+  KSC_HIP(scratch_address(&base));
+  hipStream_t s = static_cast<hipStream_t>(hip_stream);
+  return dtype == KSC_F64 ? eval_J_noalloc_t<double>(d, n_curves, state, J2, s, base)
+                          : eval_J_noalloc_t<float>(d, n_curves, state, J2, s, base);
 }
 
 ksc_status ksc_query_flags(ksc_problem* p, uint32_t* flags_host) {
