@@ -135,8 +135,6 @@ def descend_to(backend, dtau: float, J_target: float = 1e-8, max_steps: int = 10
         arr, active, log = load_checkpoint(checkpoint)
         if log.dtype == "f64" and backend.dtype != "f64":
             backend = backend.promote()
-            if momentum > 0:
-                backend.set_momentum(momentum)
         backend.restore(arr)
         dtau = log.dtau
     backend.set_active(active)
@@ -146,7 +144,8 @@ def descend_to(backend, dtau: float, J_target: float = 1e-8, max_steps: int = 10
     stall = np.zeros(nc, dtype=int)
     log.converged = J_prev < J_target
     since_ckpt = 0
-    momentum_on = bool(momentum > 0 and resume and log.dtype == "f64")
+    momentum_on = False
+    switched_at = log.steps if log.dtype == "f64" else 1 << 62
     while log.steps < max_steps:
         n = min(chunk, max_steps - log.steps)
         n = max(every, (n // every) * every)
@@ -177,6 +176,14 @@ def descend_to(backend, dtau: float, J_target: float = 1e-8, max_steps: int = 10
             log.Jarc_history.append((log.steps, Ja.copy()))
         if progress is not None:
             progress(log, Jn)
+        if momentum > 0 and not momentum_on and backend.dtype == "f64" and \
+                log.steps > switched_at:
+            # momentum from the second FP64 chunk on: the first plain FP64
+            # chunk removes the FP32 rounding noise, whose fast initial decrease
+            # would otherwise throw the heavy ball out of the basin
+            backend.set_momentum(momentum)
+            momentum_on = True
+            log.events.append((log.steps, f"momentum {momentum} on"))
         improved = Jn < best * (1 - 1e-7)
         stall = np.where(improved, 0, stall + 1)
         best = np.minimum(best, Jn)
@@ -198,11 +205,9 @@ def descend_to(backend, dtau: float, J_target: float = 1e-8, max_steps: int = 10
             if np.any(need):
                 backend = backend.promote()
                 backend.set_active(active)
-                if momentum > 0:
-                    backend.set_momentum(momentum)
-                    momentum_on = True
                 log.dtype = "f64"
                 log.events.append((log.steps, "switched to FP64"))
+                switched_at = log.steps
                 last_good = backend.snapshot()
                 stall[:] = 0
         since_ckpt += n
