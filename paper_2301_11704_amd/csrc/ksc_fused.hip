@@ -23,7 +23,9 @@ __global__ __launch_bounds__(64 * W) void fused_kernel(KernelArgs<T> a) {
       tile_copy<NX, T, W>(a, cd, td.curve, td.j0, tile);
       continue;
     }
-    if constexpr (lanes_per_row<NX, T>() == 2)
+    if constexpr (lanes_per_row<NX, T>() > 2)
+      tile_body_lanes<NX, T, W, MODE, lanes_per_row<NX, T>()>(a, cd, td.curve, td.j0, tile, buf);
+    else if constexpr (lanes_per_row<NX, T>() == 2)
       tile_body2<NX, T, W, MODE>(a, cd, td.curve, td.j0, tile, buf);
     else
       tile_body<NX, T, W, MODE>(a, cd, td.curve, td.j0, tile, buf, red);
@@ -116,6 +118,8 @@ template <typename T, int W, int NX>
 constexpr bool tile_fits() {
   constexpr int KM = (NX - 1) / 3 + 1;
   constexpr int R = 64 * W / lanes_per_row<NX, T>();
+  if constexpr (lanes_per_row<NX, T>() > 2)
+    return lanes_lds_bytes(NX, KM, R, int(sizeof(T))) <= 160 * 1024;
   return ((R + 2) * KM + 2) * int(sizeof(cplx<T>)) + 64 * W * u_stash<NX, T>() * int(sizeof(T)) <=
          160 * 1024;
 }

@@ -333,7 +333,8 @@ namespace {
 // Lanes per row (mirrors lanes_per_row<NX, T>() of the kernels) and rows per
 // tile of W waves for grid size nx.
 int lanes_per_row(const ksc_problem* p, int nx) {
-  if (p->odd()) return 1;
+  if (p->odd() || p->spectral()) return 1;
+  if (p->esize() == 4 && nx == 256) return 8;  // tile_body_lanes
   return nx * int(p->esize()) > 512 ? 2 : 1;
 }
 int rows_per_tile(const ksc_problem* p, int W, int nx) { return 64 * W / lanes_per_row(p, nx); }
@@ -348,11 +349,13 @@ size_t lds_for(const ksc_problem* p, int W, int nx) {
   // (odd subspace: the last 16-byte chunk of a staged block may start up to
   // 16 bytes past the block and end 16 bytes after that)
   if (p->odd()) return size_t(rows_per_tile(p, W, nx) + 2) * (modes_of(nx) - 1) * p->esize() + 32;
+  if (lanes_per_row(p, nx) > 2)
+    return size_t(ksc::lanes_lds_bytes(nx, modes_of(nx), rows_per_tile(p, W, nx), int(p->esize())));
   const size_t cs = 2 * p->esize();
   // plus the samples of u that each lane parks in LDS between the passes
   // (ksc::u_stash of the tile kernels)
   const size_t stash = (p->esize() == 4) ? size_t(64 * W) * ksc::u_stash<128, float>() * 4 : 0;
-  const size_t park = (nx == 128 || nx == 256) ? stash : 0;
+  const size_t park = (nx == 128) ? stash : 0;
   return (size_t(rows_per_tile(p, W, nx) + 2) * modes_of(nx) + 2) * cs + park;
 }
 // Largest staging buffer over the grid sizes of the problem (one launch may
@@ -1173,7 +1176,7 @@ __global__ __launch_bounds__(256) void noalloc_reduce_kernel(const double* part,
 template <typename T>
 ksc_status eval_J_noalloc_t(const ksc_curve_desc& d, int n_curves, const void* state, double* J2,
                             hipStream_t s, void* base) {
-  const int lanes = (d.n_x * int(sizeof(T)) > 512) ? 2 : 1;
+  const int lanes = (sizeof(T) == 4 && d.n_x == 256) ? 8 : (d.n_x * int(sizeof(T)) > 512) ? 2 : 1;
   const int km = modes_of(d.n_x);
   int dev = 0;
   KSC_HIP(hipGetDevice(&dev));
@@ -1185,9 +1188,11 @@ ksc_status eval_J_noalloc_t(const ksc_curve_desc& d, int n_curves, const void* s
   size_t lds = 0;
   for (int w : {4, 2, 1}) {
     const size_t rows = size_t(64 * w / lanes) + 2;
-    const size_t park = (sizeof(T) == 4 && (d.n_x == 128 || d.n_x == 256))
+    const size_t park = (sizeof(T) == 4 && d.n_x == 128)
                             ? size_t(64 * w) * ksc::u_stash<128, float>() * 4 : 0;
-    const size_t b = (rows * km + 2) * 2 * sizeof(T) + park;
+    const size_t b = (lanes > 2)
+                         ? size_t(ksc::lanes_lds_bytes(d.n_x, km, 64 * w / lanes, int(sizeof(T))))
+                         : (rows * km + 2) * 2 * sizeof(T) + park;
     if (b <= size_t(lds_dev)) {
       W = w;
       lds = b;

@@ -1,0 +1,370 @@
+// Rows split over L lanes: the fused tile evaluation for grids whose row is
+// too wide for one lane (N_x = 256 in FP32), with every row's transforms
+// spread over L consecutive lanes so that a long curve fills the chip.
+//
+// Layout of one row over its L lanes (lane p = 0..L-1 of the row's group),
+// with the half-length trick z_m = x_{2m} + i x_{2m+1}, m < M = N/2 = L Q:
+//   spectrum side: lane p holds the coefficients k = L k1 + p, k1 < Q;
+//   sample side:   lane p holds z_m for m = m1 + Q m2 with m1 = p Q/L + j,
+//                  j < Q/L, m2 < L, at index j L + m2.
+// The M-point DFT splits as  z_{m1 + Q m2} = sum_p w_L^{m2 p} w_M^{m1 p}
+// sum_{k1} w_Q^{m1 k1} Z_{L k1 + p}:  a Q-point FFT in each lane, a twiddle,
+// a transpose of the row's L x Q block through LDS, and Q/L L-point FFTs in
+// each lane (the forward transform runs the same steps in reverse).  The
+// transpose moves data through LDS instead of cross-lane butterflies, so the
+// arithmetic is that of the single-lane transform plus one twiddle per point.
+//
+// Pass 0 (u = c2r(u_hat), N_hat = r2c(u^2), the residual) runs in FP64 as in
+// the one-lane kernel; the residual rows are exchanged between neighbouring
+// rows in FP64 as well, so that the adjoint's d/ds differences unrounded
+// residuals.
+#pragma once
+
+#include "ksc_tile.hpp"
+
+namespace ksc {
+
+// LDS footprint (bytes) of the L-lane tile of W waves: staging rows (state
+// dtype), residual rows (FP64), the transpose blocks (FP64, one row of M
+// complex values per tile row) and the twiddle table e^{2 pi i j / N} (FP64).
+constexpr int lanes_stage_bytes(int KM, int R, int esize) {
+  return ((((R + 2) * KM + 2) * 2 * esize) + 15) / 16 * 16;
+}
+constexpr int lanes_lds_bytes(int NX, int KM, int R, int esize) {
+  return lanes_stage_bytes(KM, R, esize) + (R + 2) * KM * 16 + R * (NX / 2) * 16 + NX * 16;
+}
+
+namespace lanes_detail {
+
+template <typename T>
+__device__ __forceinline__ cplx<T> cmul(cplx<T> a, cplx<T> b) {
+  return cplx<T>{fmaT(a.r, b.r, -a.i * b.i), fmaT(a.r, b.i, a.i * b.r)};
+}
+template <typename T>
+__device__ __forceinline__ cplx<T> cmulc(cplx<T> a, cplx<T> b) {  // a conj(b)
+  return cplx<T>{fmaT(a.r, b.r, a.i * b.i), fmaT(a.i, b.r, -a.r * b.i)};
+}
+template <typename T>
+__device__ __forceinline__ cplx<T> tw_get(const cplx<double>* tw, int idx) {
+  const cplx<double> w = tw[idx];
+  return cplx<T>{T(w.r), T(w.i)};
+}
+
+}  // namespace lanes_detail
+
+// Band-limited spectrum -> this lane's samples (layout above).  X(k) returns
+// coefficient k (0 for k > K; Im of mode 0 ignored); tb: the row's transpose
+// block in LDS (M complex of type T); tw: e^{2 pi i j / N}, j < N.  Every lane
+// of the workgroup must call it together (it synchronizes the workgroup).
+template <int N, int L, typename T, class XF>
+__device__ __forceinline__ void c2r_lanes(XF X, int p, cplx<T>* tb, const cplx<double>* tw,
+                                          T (&out)[N / L]) {
+  using namespace lanes_detail;
+  constexpr int M = N / 2, Q = M / L, QL = Q / L;
+  static_assert(Q % L == 0, "Q must be a multiple of L");
+  T zr[Q], zi[Q];
+  sfor<Q>([&](auto K1) {
+    constexpr int k1 = K1;
+    const int k = L * k1 + p;
+    const cplx<T> a = X(k);
+    cplx<T> b = X(M - k);  // zero for k = 0 (coefficient M is above K)
+    b.i = -b.i;            // conj
+    const cplx<T> E{a.r + b.r, a.i + b.i};
+    const cplx<T> O = cmul(cplx<T>{a.r - b.r, a.i - b.i}, tw_get<T>(tw, k));
+    zr[k1] = E.r - O.i;  // Z = E + i O
+    zi[k1] = E.i + O.r;
+  });
+  fft_c<Q, +1, T>(zr, zi);
+  sfor<Q>([&](auto M1) {
+    constexpr int m1 = M1;
+    const cplx<T> y = cmul(cplx<T>{zr[m1], zi[m1]}, tw_get<T>(tw, (2 * m1 * p) % N));
+    tb[m1 * L + p] = y;
+  });
+  __syncthreads();
+  sfor<QL>([&](auto J) {
+    constexpr int j = J;
+    const int m1 = p * QL + j;
+    T tr[L], ti[L];
+    sfor<L>([&](auto Qq) {
+      constexpr int q = Qq;
+      const cplx<T> v = tb[m1 * L + q];
+      tr[q] = v.r;
+      ti[q] = v.i;
+    });
+    fft_c<L, +1, T>(tr, ti);
+    sfor<L>([&](auto M2) {
+      constexpr int m2 = M2;
+      out[2 * (j * L + m2)] = tr[m2];
+      out[2 * (j * L + m2) + 1] = ti[m2];
+    });
+  });
+  __syncthreads();
+}
+
+// This lane's samples -> its kept coefficients, unnormalized and doubled:
+//   X_k = 2 sum_n x_n e^{-2 pi i k n / N} for k = L i + p <= K (X[i]).
+template <int N, int KM, int L, typename T>
+__device__ __forceinline__ void r2c_lanes(const T (&in)[N / L], int p, cplx<T>* tb,
+                                          const cplx<double>* tw,
+                                          cplx<T> (&X)[(KM + L - 1) / L]) {
+  using namespace lanes_detail;
+  constexpr int M = N / 2, Q = M / L, QL = Q / L, KL = (KM + L - 1) / L;
+  sfor<QL>([&](auto J) {
+    constexpr int j = J;
+    const int m1 = p * QL + j;
+    T tr[L], ti[L];
+    sfor<L>([&](auto M2) {
+      constexpr int m2 = M2;
+      tr[m2] = in[2 * (j * L + m2)];
+      ti[m2] = in[2 * (j * L + m2) + 1];
+    });
+    fft_c<L, -1, T>(tr, ti);
+    sfor<L>([&](auto Qq) {
+      constexpr int q = Qq;
+      tb[m1 * L + q] = cplx<T>{tr[q], ti[q]};
+    });
+  });
+  __syncthreads();
+  T zr[Q], zi[Q];
+  sfor<Q>([&](auto M1) {
+    constexpr int m1 = M1;
+    const cplx<T> w = cmulc(tb[m1 * L + p], tw_get<T>(tw, (2 * m1 * p) % N));
+    zr[m1] = w.r;
+    zi[m1] = w.i;
+  });
+  __syncthreads();
+  fft_c<Q, -1, T>(zr, zi);  // Z_{L k1 + p} at k1
+  sfor<Q>([&](auto K1) {
+    constexpr int k1 = K1;
+    tb[L * k1 + p] = cplx<T>{zr[k1], zi[k1]};
+  });
+  __syncthreads();
+  sfor<KL>([&](auto I) {
+    constexpr int i = I;
+    const int k = L * i + p;
+    const cplx<T> zb = tb[(M - k) % M];  // Z_{M-k}
+    const T Dr = zr[i] + zb.r, Di = zi[i] - zb.i;
+    const cplx<T> S{zr[i] - zb.r, zi[i] + zb.i};
+    const cplx<T> V = cmulc(S, tw_get<T>(tw, k));  // e^{-2 pi i k / N} S
+    X[i] = cplx<T>{Dr + V.i, Di - V.r};
+  });
+  __syncthreads();
+}
+
+template <int NX, typename T, int W, int MODE, int L>
+__device__ __forceinline__ void tile_body_lanes(const KernelArgs<T>& a, const CurveDev& cd, int c,
+                                                int j0, int tile, cplx<T>* buf) {
+  using namespace lanes_detail;
+  constexpr int KM = (NX - 1) / 3 + 1;
+  constexpr int KL = (KM + L - 1) / L;  // modes per lane
+  constexpr int NT = 64 * W;            // lanes
+  constexpr int ROWS = NT / L;          // rows per tile
+  constexpr int BR = ROWS + 2;          // staged rows: j0-1 .. j0+ROWS
+  constexpr int E = 16 / int(sizeof(cplx<T>));
+  constexpr int M = NX / 2;
+  constexpr int NS = NX / L;            // samples per lane
+  const int t = threadIdx.x / L;        // row within the tile
+  const int p = threadIdx.x % L;
+  const int n_s = cd.n_s;
+  const int jr = j0 + t;
+  const bool interior = (jr >= 1) && (jr <= n_s - 2);
+
+  // LDS: staging rows (dtype T), residual rows (FP64), transpose blocks
+  // (FP64), twiddles (FP64)
+  cplx<double>* r64 = reinterpret_cast<cplx<double>*>(
+      reinterpret_cast<char*>(buf) + lanes_stage_bytes(KM, ROWS, int(sizeof(T))));
+  cplx<double>* tbd = r64 + BR * KM + t * M;  // this row's transpose block
+  cplx<double>* tw = r64 + BR * KM + ROWS * M;
+
+  const long long base = cd.off + (long long)(j0 - 1) * KM;
+  const int sh = int(((base % E) + E) % E);
+  __syncthreads();  // the previous tile of a persistent workgroup is done with the LDS
+  for (int j = threadIdx.x; j < NX; j += NT) {
+    double s, co;
+    sincospi(2.0 * j / NX, &s, &co);
+    tw[j] = cplx<double>{co, s};
+  }
+  stage_block<cplx<T>, NT, BR * KM + E>(buf, a.in, base, sh, BR * KM + sh,
+                                        cd.off + (long long)(j0 > 0 ? j0 - 1 : 0) * KM,
+                                        cd.off + (long long)min(n_s, j0 + ROWS + 1) * KM);
+  __syncthreads();
+  cplx<T>* __restrict__ rows = buf + sh;
+  const cplx<T>* __restrict__ my = rows + (t + 1) * KM;
+
+  const T x0i = my[0].i;  // raw Im u_hat_0 (lane 0 of the row uses it)
+  const T csj = interior ? a.cs[cd.row_off + jr] : T(0);
+
+  // ---- pass 0 in FP64: u, S0 = r2c(u^2) = 2 N_x N_hat of the lane's modes ----
+  T u[MODE == MODE_J ? 1 : NS];
+  cplx<double> S0[KL];
+  {
+    double v[NS];
+    c2r_lanes<NX, L, double>(
+        [&](int k) {
+          cplx<double> x{0.0, 0.0};
+          if (k < KM) {
+            const cplx<T> y = my[k];
+            x = cplx<double>{double(y.r), k == 0 ? 0.0 : double(y.i)};
+          }
+          return x;
+        },
+        p, tbd, tw, v);
+    if constexpr (MODE != MODE_J) {
+      sfor<NS>([&](auto Nn) {
+        constexpr int n = Nn;
+        u[n] = T(v[n]);
+      });
+    }
+    sfor<NS>([&](auto Nn) {
+      constexpr int n = Nn;
+      v[n] = v[n] * v[n];
+    });
+    r2c_lanes<NX, KM, L, double>(v, p, tbd, tw, S0);
+  }
+
+  // ---- residual of the lane's modes (FP64), its row sums ----
+  double rowR = 0.0, rowD = 0.0;  // sum of c_k |r_k|^2, c_k |du_k|^2 over the lane's modes
+  cplx<double> R[KL];
+  {
+    const double q1 = cd.q1, qN1 = cd.q1 / (4.0 * NX), cs_r = double(csj);
+    sfor<KL>([&](auto I) {
+      constexpr int i = I;
+      const int k = L * i + p;
+      double rr = 0.0, ri = 0.0, dr = 0.0, di = 0.0;
+      if (k < KM) {
+        const cplx<T> xm = rows[t * KM + k], x0 = my[k], xp = rows[(t + 2) * KM + k];
+        dr = double(xp.r) - double(xm.r);
+        di = (k == 0) ? 0.0 : double(xp.i) - double(xm.i);
+        const double qk = double(k) * q1;
+        const double q2 = qk * qk;
+        const double Ak = fmaT(-q2, q2, q2);
+        const double qn = double(k) * qN1;
+        rr = fmaT(-cs_r, dr, fmaT(Ak, double(x0.r), qn * S0[i].i));
+        ri = (k == 0) ? 0.0 : fmaT(-cs_r, di, fmaT(Ak, double(x0.i), -qn * S0[i].r));
+      }
+      if (!interior) rr = ri = 0.0;
+      R[i] = cplx<double>{rr, ri};
+      const double ck = (k == 0) ? 1.0 : 2.0;
+      rowR = fmaT(ck, fmaT(rr, rr, ri * ri), rowR);
+      if constexpr (MODE == MODE_J) rowD = fmaT(ck, fmaT(dr, dr, di * di), rowD);
+    });
+    double pj = 0.0, pn = 0.0, pd = 0.0;
+    const double wl = interior ? a.wlD[cd.row_off + jr] : 0.0;
+    pj = wl * rowR;
+    if constexpr (MODE == MODE_J) {
+      // J_arc needs whole-row norms: add the L lanes' shares
+      double rRrow = rowR, rDrow = rowD;
+      sfor<ilog2(L)>([&](auto B) {
+        constexpr int b = 1 << int(B);
+        rRrow += __shfl_xor(rRrow, b, 64);
+        rDrow += __shfl_xor(rDrow, b, 64);
+      });
+      if (interior && p == 0) {
+        pn = sqrt(rRrow * rDrow);
+        pd = sqrt(rDrow);
+      }
+    }
+    store_wave_partials<W, (MODE == MODE_J) ? 3 : 1>(pj, pn, pd, tile_partials(a, cd, c, tile, W));
+  }
+  if constexpr (MODE != MODE_J) {
+  // ---- exchange residual rows (FP64) ----
+  sfor<KL>([&](auto I) {
+    constexpr int i = I;
+    const int k = L * i + p;
+    if (k < KM) r64[(t + 1) * KM + k] = R[i];
+  });
+  for (int i = threadIdx.x; i < 2 * KM; i += NT)
+    r64[(i < KM) ? i : (BR - 2) * KM + i] = cplx<double>{0.0, 0.0};
+  __syncthreads();
+
+  // ---- pass 1 in the state dtype: S = r2c(u * c2r(i q r_hat / (2 N_x))) = Q_hat ----
+  cplx<T> S[KL];
+  {
+    const cplx<double>* rme = r64 + (t + 1) * KM;
+    const T qY1 = T(cd.q1 / (2.0 * NX));
+    cplx<T>* tbt = reinterpret_cast<cplx<T>*>(tbd);
+    T v[NS];
+    c2r_lanes<NX, L, T>(
+        [&](int k) {
+          cplx<T> x{T(0), T(0)};
+          if (k < KM) {
+            const cplx<double> y = rme[k];
+            const T qk = T(k) * qY1;
+            x = cplx<T>{-qk * T(y.i), qk * T(y.r)};
+          }
+          return x;
+        },
+        p, tbt, tw, v);
+    sfor<NS>([&](auto Nn) {
+      constexpr int n = Nn;
+      v[n] = u[n] * v[n];
+    });
+    r2c_lanes<NX, KM, L, T>(v, p, tbt, tw, S);
+  }
+
+  // ---- L^dagger r = g (r_{j+1} - r_{j-1}) / (2 dsigma) + Q_hat + A r_hat ----
+  const bool fix_lo = interior && t == 0 && jr - 1 >= 1;
+  const bool fix_hi = interior && t == ROWS - 1 && jr + 1 <= n_s - 2;
+  cplx<T> D[KL];
+  {
+    const double q1 = cd.q1, cs_r = double(csj);
+    sfor<KL>([&](auto I) {
+      constexpr int i = I;
+      const int k = L * i + p;
+      D[i] = cplx<T>{T(0), T(0)};
+      if (k < KM) {
+        const cplx<double> rm = r64[t * KM + k], rp = r64[(t + 2) * KM + k];
+        const double qk = double(k) * q1;
+        const double q2 = qk * qk;
+        const double Ak = fmaT(-q2, q2, q2);
+        const double dr = fmaT(cs_r, rp.r - rm.r, fmaT(Ak, R[i].r, double(S[i].r)));
+        const double di = fmaT(cs_r, rp.i - rm.i, fmaT(Ak, R[i].i, double(S[i].i)));
+        D[i] = cplx<T>{T(dr), (k == 0) ? T(0) : T(di)};
+      }
+    });
+  }
+  if (fix_lo || fix_hi) {
+    cplx<T>* e = a.edge + ((long long)tile * 4 + (fix_hi ? 2 : 0)) * a.km_max;
+    sfor<KL>([&](auto I) {
+      constexpr int i = I;
+      const int k = L * i + p;
+      if (k < KM) {
+        e[k] = D[i];
+        e[a.km_max + k] = cplx<T>{T(R[i].r), T(R[i].i)};
+      }
+    });
+  }
+  // ---- the tile's output rows, staged in LDS and written back coalesced ----
+  const long long obase = cd.off + (long long)j0 * KM;
+  const int osh = int(obase % E);
+  cplx<T>* __restrict__ orow = buf + osh + t * KM;
+  __syncthreads();  // every lane has read its state rows
+  if constexpr (MODE == MODE_GRAD) {
+    const T sc = (a.scale != nullptr) ? T(a.scale[c]) : T(1);
+    const T f0 = interior ? a.wlT[cd.row_off + jr] * sc : T(0);
+    sfor<KL>([&](auto I) {
+      constexpr int i = I;
+      const int k = L * i + p;
+      const T f = (k == 0) ? f0 : T(2) * f0;  // c_0 = 1, c_k = 2
+      if (k < KM) orow[k] = cplx<T>{f * D[i].r, f * D[i].i};
+    });
+  } else {
+    const T* __restrict__ pv = a.pre + cd.mode_off;
+    const T m = interior ? T(1) : T(0);
+    sfor<KL>([&](auto I) {
+      constexpr int i = I;
+      const int k = L * i + p;
+      if (k < KM) {
+        const T f = m * pv[k];
+        orow[k] = cplx<T>{f * D[i].r, (k == 0) ? -x0i : f * D[i].i};
+      }
+    });
+  }
+  __syncthreads();
+  flush_block<cplx<T>, NT, ROWS * KM + E, MODE == MODE_STEP>(
+      a.out, a.in, buf, obase, osh, ROWS * KM + osh, obase,
+      cd.off + (long long)min(n_s, j0 + ROWS) * KM);
+  }  // MODE != MODE_J
+}
+
+}  // namespace ksc

@@ -5,7 +5,7 @@
 #include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
-#include "ksc_tile.hpp"
+#include "ksc_lanes.hpp"
 
 namespace ksc {
 

@@ -254,12 +254,11 @@ __device__ __forceinline__ void flush_block(V* __restrict__ gout, const V* __res
 // Samples of the physical field u that a lane parks in LDS between the two
 // passes of the gradient (the rest stay in registers).  Only where pass 0's
 // FP64 transform work space would not fit next to the whole field: N_x = 128
-// with one FP32 row per lane, N_x = 256 with an FP32 row per lane pair (128
-// samples per lane either way).  The host adds lanes * u_stash * sizeof(T)
+// with one FP32 row per lane.  The host adds lanes * u_stash * sizeof(T)
 // bytes to the staging buffer's LDS.
 template <int NX, typename T>
 constexpr int u_stash() {
-  return (sizeof(T) == 4 && (NX == 128 || NX == 256)) ? 64 : 0;
+  return (sizeof(T) == 4 && NX == 128) ? 64 : 0;
 }
 
 template <int NX, typename T, int W, int MODE>
@@ -516,6 +515,7 @@ __device__ __forceinline__ void tile_body(const KernelArgs<T>& a, const CurveDev
 // transform work space), else a lane pair per row.
 template <int NX, typename T>
 constexpr int lanes_per_row() {
+  if (sizeof(T) == 4 && NX == 256) return 8;  // ksc_lanes.hpp
   return (NX * int(sizeof(T)) > 512) ? 2 : 1;
 }
 

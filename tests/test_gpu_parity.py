@@ -331,12 +331,7 @@ def test_config2_full_size_parity():
     e = (precond_rel_err(c, Gg, Gr), elementwise_rel_err(c, Gg, Gr),
          directional_rel_err(c, Gg, Gr, [(8, i) for i in range(16)]))
     print("workload 2 gradient errors (preconditioned, element-wise, directional):", e, flush=True)
-    assert e[0] <= 1e-5 and e[2] <= 1e-5, e
-    # element-wise: the adjoint differences residual rows that the lane-pair
-    # kernel exchanges rounded to FP32; at N_s = 8192 one element of the
-    # weighted gradient is off by 1.2e-5 of the largest (an FP32 emulation of
-    # the same arithmetic on the CPU gives the same figure)
-    assert e[1] <= 2e-5, e
+    assert max(e) <= 1e-5, e
     St, Sr = prob.download(Y, 0), oracle.step(c, U, 1e-4)
     assert np.abs(St - Sr).max() <= 1e-5 * np.abs(Sr).max()
 
