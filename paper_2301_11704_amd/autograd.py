@@ -20,14 +20,17 @@ class KSCurveJ2(torch.autograd.Function):
     def forward(ctx, state: torch.Tensor, prob: Problem):
         ctx.prob = prob
         ctx.save_for_backward(state)
-        return prob.eval_J(state.detach().contiguous())
+        return prob.eval_J(state if state.is_contiguous() else state.contiguous())
 
     @staticmethod
     def backward(ctx, gJ2: torch.Tensor):
         (state,) = ctx.saved_tensors
         prob: Problem = ctx.prob
-        scale = gJ2.detach().to(torch.float64).contiguous()
-        grad, _ = prob.eval_grad(state.detach().contiguous(), scale=scale, want_J2=False)
+        scale = gJ2 if gJ2.dtype == torch.float64 else gJ2.to(torch.float64)
+        if not scale.is_contiguous():  # e.g. the expanded upstream of a sum
+            scale = scale.contiguous()
+        grad, _ = prob.eval_grad(state if state.is_contiguous() else state.contiguous(),
+                                 scale=scale, want_J2=False)
         return grad, None
 
 

@@ -10,7 +10,7 @@
 namespace ksc {
 
 template <int NX, typename T, int W, int MODE>
-__global__ __launch_bounds__(64 * W) void fused_kernel(KernelArgs<T> a) {
+__global__ __launch_bounds__(64 * W, (tile_waves_per_simd<NX, T>())) void fused_kernel(KernelArgs<T> a) {
   extern __shared__ __align__(16) double smem_d[];
   constexpr int KM = (NX - 1) / 3 + 1;
   cplx<T>* buf = reinterpret_cast<cplx<T>*>(smem_d);
@@ -119,7 +119,7 @@ constexpr bool tile_fits() {
   constexpr int KM = (NX - 1) / 3 + 1;
   constexpr int R = 64 * W / lanes_per_row<NX, T>();
   if constexpr (lanes_per_row<NX, T>() > 2)
-    return lanes_lds_bytes(NX, KM, R, int(sizeof(T))) <= 160 * 1024;
+    return lanes_lds_bytes(NX, KM, R, lanes_per_row<NX, T>(), int(sizeof(T))) <= 160 * 1024;
   return ((R + 2) * KM + 2) * int(sizeof(cplx<T>)) + 64 * W * u_stash<NX, T>() * int(sizeof(T)) <=
          160 * 1024;
 }

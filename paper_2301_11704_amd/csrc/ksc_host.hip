@@ -110,10 +110,10 @@ __device__ __forceinline__ double wave_sum_fixed(double v) {
 }
 
 // Runs after every fused launch (256 threads per block).
-//  * blocks [0, fin_blocks): one wave per curve loads its tiles' FP64 partials
-//    in parallel (lane i takes tiles i, i+64, ...) and sums them with a fixed
-//    reduction tree into J2 and J_arc = sqrt(L) num/den; raises the curve's
-//    flags (non-finite cost; with track, a rise of the cost).
+//  * blocks [0, fin_blocks): one block per curve loads its tiles' FP64
+//    partials in parallel (thread i takes slots i, i+256, ...) and sums them
+//    with a fixed reduction tree into J2 and J_arc = sqrt(L) num/den; raises
+//    the curve's flags (non-finite cost; with track, a rise of the cost).
 //  * the other blocks: one thread per (tile boundary, mode) completes the two
 //    boundary rows L | F = L+1 of a curve, whose neighbouring residual row was
 //    computed by the other tile:  adj_L += cs_L r_F,  adj_F -= cs_F r_L, and
@@ -121,9 +121,7 @@ __device__ __forceinline__ double wave_sum_fixed(double v) {
 template <typename T>
 __global__ __launch_bounds__(256) void post_kernel(PostArgs<T> a) {
   if (int(blockIdx.x) < a.fin_blocks) {
-    const int c = blockIdx.x * 4 + (threadIdx.x >> 6);
-    const int lane = threadIdx.x & 63;
-    if (c >= a.nc) return;
+    const int c = blockIdx.x;
     if (a.active != nullptr && a.active[c] == 0) return;
     double s0 = 0, s1 = 0, s2 = 0;
     long long first;
@@ -137,16 +135,41 @@ __global__ __launch_bounds__(256) void post_kernel(PostArgs<T> a) {
       first = (long long)cd.tile_begin * a.waves;
       nw = cd.n_tiles * a.waves;
     }
-    for (int t = lane; t < nw; t += 64) {
-      const double* p = a.partials + 3 * (first + t);
-      s0 += p[0];
-      s1 += p[1];
-      s2 += p[2];
+    // thread i adds the slots i, i + 256, ... in that order, four loads in
+    // flight at a time
+    for (int t0 = threadIdx.x; t0 < nw; t0 += 1024) {
+      double v[4][3];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int t = t0 + 256 * u;
+        const double* p = a.partials + 3 * (first + t);
+        v[u][0] = (t < nw) ? p[0] : 0.0;
+        v[u][1] = (t < nw) ? p[1] : 0.0;
+        v[u][2] = (t < nw) ? p[2] : 0.0;
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        s0 += v[u][0];
+        s1 += v[u][1];
+        s2 += v[u][2];
+      }
     }
     s0 = wave_sum_fixed(s0);
     s1 = wave_sum_fixed(s1);
     s2 = wave_sum_fixed(s2);
-    if (lane != 0) return;
+    // the four wave sums, added in a fixed order
+    __shared__ double wsum[4][3];
+    const int wv = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0) {
+      wsum[wv][0] = s0;
+      wsum[wv][1] = s1;
+      wsum[wv][2] = s2;
+    }
+    __syncthreads();
+    if (threadIdx.x != 0) return;
+    s0 = (wsum[0][0] + wsum[1][0]) + (wsum[2][0] + wsum[3][0]);
+    s1 = (wsum[0][1] + wsum[1][1]) + (wsum[2][1] + wsum[3][1]);
+    s2 = (wsum[0][2] + wsum[1][2]) + (wsum[2][2] + wsum[3][2]);
     if (a.J2) a.J2[c] = s0;
     if (a.Jarc) a.Jarc[c] = (s2 > 0) ? a.sqrtL[c] * s1 / s2 : 0.0;
     unsigned f = 0;
@@ -334,7 +357,7 @@ namespace {
 // tile of W waves for grid size nx.
 int lanes_per_row(const ksc_problem* p, int nx) {
   if (p->odd() || p->spectral()) return 1;
-  if (p->esize() == 4 && nx == 256) return 8;  // tile_body_lanes
+  if (p->esize() == 4 && nx == 256) return ksc::kLanesF32N256;  // tile_body_lanes
   return nx * int(p->esize()) > 512 ? 2 : 1;
 }
 int rows_per_tile(const ksc_problem* p, int W, int nx) { return 64 * W / lanes_per_row(p, nx); }
@@ -350,7 +373,8 @@ size_t lds_for(const ksc_problem* p, int W, int nx) {
   // 16 bytes past the block and end 16 bytes after that)
   if (p->odd()) return size_t(rows_per_tile(p, W, nx) + 2) * (modes_of(nx) - 1) * p->esize() + 32;
   if (lanes_per_row(p, nx) > 2)
-    return size_t(ksc::lanes_lds_bytes(nx, modes_of(nx), rows_per_tile(p, W, nx), int(p->esize())));
+    return size_t(ksc::lanes_lds_bytes(nx, modes_of(nx), rows_per_tile(p, W, nx),
+                                       lanes_per_row(p, nx), int(p->esize())));
   const size_t cs = 2 * p->esize();
   // plus the samples of u that each lane parks in LDS between the passes
   // (ksc::u_stash of the tile kernels)
@@ -627,7 +651,7 @@ ksc_status launch_post(ksc_problem* p, int mode, const void* in, void* out, cons
   a.active = active;
   a.track = track;
   const int b = 256;
-  a.fin_blocks = finalize ? (p->nc + 3) / 4 : 0;
+  a.fin_blocks = finalize ? p->nc : 0;
   a.mode = mode;
   a.odd = p->odd() ? 1 : 0;
   a.waves = p->W;
@@ -1176,7 +1200,8 @@ __global__ __launch_bounds__(256) void noalloc_reduce_kernel(const double* part,
 template <typename T>
 ksc_status eval_J_noalloc_t(const ksc_curve_desc& d, int n_curves, const void* state, double* J2,
                             hipStream_t s, void* base) {
-  const int lanes = (sizeof(T) == 4 && d.n_x == 256) ? 8 : (d.n_x * int(sizeof(T)) > 512) ? 2 : 1;
+  const int lanes = (sizeof(T) == 4 && d.n_x == 256) ? ksc::kLanesF32N256
+                    : (d.n_x * int(sizeof(T)) > 512) ? 2 : 1;
   const int km = modes_of(d.n_x);
   int dev = 0;
   KSC_HIP(hipGetDevice(&dev));
@@ -1191,7 +1216,7 @@ ksc_status eval_J_noalloc_t(const ksc_curve_desc& d, int n_curves, const void* s
     const size_t park = (sizeof(T) == 4 && d.n_x == 128)
                             ? size_t(64 * w) * ksc::u_stash<128, float>() * 4 : 0;
     const size_t b = (lanes > 2)
-                         ? size_t(ksc::lanes_lds_bytes(d.n_x, km, 64 * w / lanes, int(sizeof(T))))
+                         ? size_t(ksc::lanes_lds_bytes(d.n_x, km, 64 * w / lanes, lanes, int(sizeof(T))))
                          : (rows * km + 2) * 2 * sizeof(T) + park;
     if (b <= size_t(lds_dev)) {
       W = w;

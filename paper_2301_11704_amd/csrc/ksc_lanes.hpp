@@ -14,6 +14,20 @@
 // transpose moves data through LDS instead of cross-lane butterflies, so the
 // arithmetic is that of the single-lane transform plus one twiddle per point.
 //
+// With L = 2Q (more lanes than points per lane) the L-point stage over p runs
+// in the lane pairs (m1, h), m1 < Q, h = 0 / 1 holding the even / odd p of
+// that m1: a Q-point FFT in each lane, then one radix-2 step across the pair
+// (a DPP lane swap), E + w_L^j O and E - w_L^j O; a lane then holds z_m for
+// m = m1 + Q (j + Q h), j < Q.  The forward transform mirrors it.
+//
+// LDS banks: in the transpose block, entry (m1, q) sits in column
+// (q + m1 / (Q/L)) mod L of row m1, so that the L lanes of a row touch L
+// different columns both when each writes its own q and when each reads the
+// L entries of its own m1 (a plain layout puts those reads Q/L * L entries
+// apart, on the same banks).  Row blocks and residual rows are padded to an
+// odd multiple of 128 bytes so that neighbouring rows use the other half of
+// the banks.
+//
 // Pass 0 (u = c2r(u_hat), N_hat = r2c(u^2), the residual) runs in FP64 as in
 // the one-lane kernel; the residual rows are exchanged between neighbouring
 // rows in FP64 as well, so that the adjoint's d/ds differences unrounded
@@ -30,8 +44,17 @@ namespace ksc {
 constexpr int lanes_stage_bytes(int KM, int R, int esize) {
   return ((((R + 2) * KM + 2) * 2 * esize) + 15) / 16 * 16;
 }
-constexpr int lanes_lds_bytes(int NX, int KM, int R, int esize) {
-  return lanes_stage_bytes(KM, R, esize) + (R + 2) * KM * 16 + R * (NX / 2) * 16 + NX * 16;
+// Padded strides (complex FP64 entries): residual rows and transpose blocks
+// (the pair-split layout pads each of its Q lines of L entries by 2).
+constexpr int lanes_rstride(int KM) { return (KM + 7) / 16 * 16 + 8; }
+constexpr int lanes_bstride(int NX, int L) {
+  return (L * L == NX) ? (NX / 2 / L) * (L + 2) : NX / 2 + 8;
+}
+// Twiddle tables: e^{2 pi i k / N} for k < N/2 and e^{2 pi i m1 p / M}, in
+// FP64 and in the state dtype.
+constexpr int lanes_lds_bytes(int NX, int KM, int R, int L, int esize) {
+  return lanes_stage_bytes(KM, R, esize) + (R + 2) * lanes_rstride(KM) * 16 +
+         R * lanes_bstride(NX, L) * 16 + NX * (16 + 8);
 }
 
 namespace lanes_detail {
@@ -44,24 +67,30 @@ template <typename T>
 __device__ __forceinline__ cplx<T> cmulc(cplx<T> a, cplx<T> b) {  // a conj(b)
   return cplx<T>{fmaT(a.r, b.r, a.i * b.i), fmaT(a.i, b.r, -a.r * b.i)};
 }
-template <typename T>
-__device__ __forceinline__ cplx<T> tw_get(const cplx<double>* tw, int idx) {
-  const cplx<double> w = tw[idx];
-  return cplx<T>{T(w.r), T(w.i)};
+
+// The L lanes of a row sit in one wave, and the LDS performs a wave's
+// accesses in the order they were issued, so the transposes of a row need no
+// workgroup barrier: only the compiler must keep each access on its side.
+__device__ __forceinline__ void row_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
 }  // namespace lanes_detail
 
 // Band-limited spectrum -> this lane's samples (layout above).  X(k) returns
 // coefficient k (0 for k > K; Im of mode 0 ignored); tb: the row's transpose
-// block in LDS (M complex of type T); tw: e^{2 pi i j / N}, j < N.  Every lane
-// of the workgroup must call it together (it synchronizes the workgroup).
+// block in LDS (M complex of type T); tw: e^{2 pi i j / N}, j < N/2, and tw2:
+// e^{2 pi i m1 p / M} at m1 L + p, both in LDS in the arithmetic type.  All L
+// lanes of the row call it together.
 template <int N, int L, typename T, class XF>
-__device__ __forceinline__ void c2r_lanes(XF X, int p, cplx<T>* tb, const cplx<double>* tw,
-                                          T (&out)[N / L]) {
+__device__ __forceinline__ void c2r_lanes(XF X, int p, cplx<T>* tb, const cplx<T>* tw,
+                                          const cplx<T>* tw2, T (&out)[N / L]) {
   using namespace lanes_detail;
   constexpr int M = N / 2, Q = M / L, QL = Q / L;
   static_assert(Q % L == 0, "Q must be a multiple of L");
+  static_assert(64 % L == 0, "a row's lanes must sit in one wave");
   T zr[Q], zi[Q];
   sfor<Q>([&](auto K1) {
     constexpr int k1 = K1;
@@ -70,24 +99,24 @@ __device__ __forceinline__ void c2r_lanes(XF X, int p, cplx<T>* tb, const cplx<d
     cplx<T> b = X(M - k);  // zero for k = 0 (coefficient M is above K)
     b.i = -b.i;            // conj
     const cplx<T> E{a.r + b.r, a.i + b.i};
-    const cplx<T> O = cmul(cplx<T>{a.r - b.r, a.i - b.i}, tw_get<T>(tw, k));
+    const cplx<T> O = cmul(cplx<T>{a.r - b.r, a.i - b.i}, tw[k]);
     zr[k1] = E.r - O.i;  // Z = E + i O
     zi[k1] = E.i + O.r;
   });
   fft_c<Q, +1, T>(zr, zi);
   sfor<Q>([&](auto M1) {
     constexpr int m1 = M1;
-    const cplx<T> y = cmul(cplx<T>{zr[m1], zi[m1]}, tw_get<T>(tw, (2 * m1 * p) % N));
-    tb[m1 * L + p] = y;
+    const cplx<T> y = cmul(cplx<T>{zr[m1], zi[m1]}, tw2[m1 * L + p]);
+    tb[m1 * L + ((p + m1 / QL) & (L - 1))] = y;
   });
-  __syncthreads();
+  row_sync();
   sfor<QL>([&](auto J) {
     constexpr int j = J;
     const int m1 = p * QL + j;
     T tr[L], ti[L];
     sfor<L>([&](auto Qq) {
       constexpr int q = Qq;
-      const cplx<T> v = tb[m1 * L + q];
+      const cplx<T> v = tb[m1 * L + ((q + p) & (L - 1))];
       tr[q] = v.r;
       ti[q] = v.i;
     });
@@ -98,14 +127,14 @@ __device__ __forceinline__ void c2r_lanes(XF X, int p, cplx<T>* tb, const cplx<d
       out[2 * (j * L + m2) + 1] = ti[m2];
     });
   });
-  __syncthreads();
+  row_sync();
 }
 
 // This lane's samples -> its kept coefficients, unnormalized and doubled:
 //   X_k = 2 sum_n x_n e^{-2 pi i k n / N} for k = L i + p <= K (X[i]).
 template <int N, int KM, int L, typename T>
 __device__ __forceinline__ void r2c_lanes(const T (&in)[N / L], int p, cplx<T>* tb,
-                                          const cplx<double>* tw,
+                                          const cplx<T>* tw, const cplx<T>* tw2,
                                           cplx<T> (&X)[(KM + L - 1) / L]) {
   using namespace lanes_detail;
   constexpr int M = N / 2, Q = M / L, QL = Q / L, KL = (KM + L - 1) / L;
@@ -121,34 +150,174 @@ __device__ __forceinline__ void r2c_lanes(const T (&in)[N / L], int p, cplx<T>* 
     fft_c<L, -1, T>(tr, ti);
     sfor<L>([&](auto Qq) {
       constexpr int q = Qq;
-      tb[m1 * L + q] = cplx<T>{tr[q], ti[q]};
+      tb[m1 * L + ((q + p) & (L - 1))] = cplx<T>{tr[q], ti[q]};
     });
   });
-  __syncthreads();
+  row_sync();
   T zr[Q], zi[Q];
   sfor<Q>([&](auto M1) {
     constexpr int m1 = M1;
-    const cplx<T> w = cmulc(tb[m1 * L + p], tw_get<T>(tw, (2 * m1 * p) % N));
+    const cplx<T> w = cmulc(tb[m1 * L + ((p + m1 / QL) & (L - 1))], tw2[m1 * L + p]);
     zr[m1] = w.r;
     zi[m1] = w.i;
   });
-  __syncthreads();
+  row_sync();
   fft_c<Q, -1, T>(zr, zi);  // Z_{L k1 + p} at k1
   sfor<Q>([&](auto K1) {
     constexpr int k1 = K1;
     tb[L * k1 + p] = cplx<T>{zr[k1], zi[k1]};
   });
-  __syncthreads();
+  row_sync();
   sfor<KL>([&](auto I) {
     constexpr int i = I;
     const int k = L * i + p;
     const cplx<T> zb = tb[(M - k) % M];  // Z_{M-k}
     const T Dr = zr[i] + zb.r, Di = zi[i] - zb.i;
     const cplx<T> S{zr[i] - zb.r, zi[i] + zb.i};
-    const cplx<T> V = cmulc(S, tw_get<T>(tw, k));  // e^{-2 pi i k / N} S
+    const cplx<T> V = cmulc(S, tw[k]);  // e^{-2 pi i k / N} S
     X[i] = cplx<T>{Dr + V.i, Di - V.r};
   });
-  __syncthreads();
+  row_sync();
+}
+
+// L = 2Q: band-limited spectrum -> this lane's samples (z_m at m = m1 + Q (j
+// + Q h), m1 = p / 2, h = p mod 2, j < Q); block entry (m1, q) at
+// m1 (L + 2) + q, which puts the 16 entries that a row's lanes read at once
+// on 16 different 16-byte bank groups.
+template <int N, int L, typename T, class XF>
+__device__ __forceinline__ void c2r_lanes_split(XF X, int p, cplx<T>* tb, const cplx<T>* tw,
+                                                const cplx<T>* tw2, T (&out)[N / L]) {
+  using namespace lanes_detail;
+  constexpr int M = N / 2, Q = M / L;
+  static_assert(L == 2 * Q && 64 % L == 0, "split layout: L = 2Q lanes in one wave");
+  T zr[Q], zi[Q];
+  sfor<Q>([&](auto K1) {
+    constexpr int k1 = K1;
+    const int k = L * k1 + p;
+    const cplx<T> a = X(k);
+    cplx<T> b = X(M - k);  // zero for k = 0 (coefficient M is above K)
+    b.i = -b.i;            // conj
+    const cplx<T> E{a.r + b.r, a.i + b.i};
+    const cplx<T> O = cmul(cplx<T>{a.r - b.r, a.i - b.i}, tw[k]);
+    zr[k1] = E.r - O.i;  // Z = E + i O
+    zi[k1] = E.i + O.r;
+  });
+  fft_c<Q, +1, T>(zr, zi);
+  cplx<T>* const tw_ = tb + p;  // entries (m1, p), m1 < Q
+  sfor<Q>([&](auto M1) {
+    constexpr int m1 = M1;
+    tw_[m1 * (L + 2)] = cmul(cplx<T>{zr[m1], zi[m1]}, tw2[m1 * L + p]);
+  });
+  row_sync();
+  const int h = p & 1;
+  const cplx<T>* const tr_ = tb + (p >> 1) * (L + 2) + h;  // entries (p / 2, 2 pp + h)
+  T vr[Q], vi[Q];
+  sfor<Q>([&](auto Pp) {
+    constexpr int pp = Pp;
+    const cplx<T> v = tr_[2 * pp];
+    vr[pp] = v.r;
+    vi[pp] = v.i;
+  });
+  row_sync();
+  fft_c<Q, +1, T>(vr, vi);  // E (h = 0) or O (h = 1) at j
+  const T sg = h ? T(-1) : T(1);
+  sfor<Q>([&](auto J) {
+    constexpr int j = J;
+    constexpr CS c = cx_unit(j, L);
+    // own value E (h = 0) or w^j O (h = 1); the pair forms E + w^j O on
+    // lane 0 and E - w^j O on lane 1
+    T orr = vr[j], oi = vi[j];
+    if constexpr (j != 0) {
+      const T gr = fmaT(T(c.c), vr[j], -T(c.s) * vi[j]);
+      const T gi = fmaT(T(c.c), vi[j], T(c.s) * vr[j]);
+      orr = h ? gr : orr;
+      oi = h ? gi : oi;
+    }
+    out[2 * j] = fmaT(sg, orr, pair_swap(orr));
+    out[2 * j + 1] = fmaT(sg, oi, pair_swap(oi));
+  });
+}
+
+// L = 2Q: this lane's samples (layout of c2r_lanes_split) -> its kept
+// coefficients, unnormalized and doubled (as r2c_lanes).
+template <int N, int KM, int L, typename T>
+__device__ __forceinline__ void r2c_lanes_split(const T (&in)[N / L], int p, cplx<T>* tb,
+                                                const cplx<T>* tw, const cplx<T>* tw2,
+                                                cplx<T> (&X)[(KM + L - 1) / L]) {
+  using namespace lanes_detail;
+  constexpr int M = N / 2, Q = M / L, KL = (KM + L - 1) / L;
+  static_assert(L == 2 * Q && KL <= Q, "split layout");
+  const int h = p & 1;
+  const T sg = h ? T(-1) : T(1);
+  T vr[Q], vi[Q];
+  sfor<Q>([&](auto J) {
+    constexpr int j = J;
+    constexpr CS c = cx_unit(j, L);
+    // lane 0: a + b, lane 1: (a - b) w^{-j}, with a = z_{m1 + Q j} (lane 0)
+    // and b = z_{m1 + Q (j + Q)} (lane 1)
+    const T ar = in[2 * j], ai = in[2 * j + 1];
+    const T tr = fmaT(sg, ar, pair_swap(ar)), ti = fmaT(sg, ai, pair_swap(ai));
+    vr[j] = tr;
+    vi[j] = ti;
+    if constexpr (j != 0) {
+      const T gr = fmaT(T(c.c), tr, T(c.s) * ti);
+      const T gi = fmaT(T(c.c), ti, -T(c.s) * tr);
+      vr[j] = h ? gr : tr;
+      vi[j] = h ? gi : ti;
+    }
+  });
+  fft_c<Q, -1, T>(vr, vi);  // entries (p / 2, 2 pp + h)
+  cplx<T>* const tr_ = tb + (p >> 1) * (L + 2) + h;
+  sfor<Q>([&](auto Pp) {
+    constexpr int pp = Pp;
+    tr_[2 * pp] = cplx<T>{vr[pp], vi[pp]};
+  });
+  row_sync();
+  T zr[Q], zi[Q];
+  const cplx<T>* const tw_ = tb + p;  // entries (m1, p)
+  sfor<Q>([&](auto M1) {
+    constexpr int mm = M1;
+    const cplx<T> w = cmulc(tw_[mm * (L + 2)], tw2[mm * L + p]);
+    zr[mm] = w.r;
+    zi[mm] = w.i;
+  });
+  row_sync();
+  fft_c<Q, -1, T>(zr, zi);  // Z_{L k1 + p} at k1
+  sfor<Q>([&](auto K1) {
+    constexpr int k1 = K1;
+    tb[L * k1 + p] = cplx<T>{zr[k1], zi[k1]};
+  });
+  row_sync();
+  sfor<KL>([&](auto I) {
+    constexpr int i = I;
+    const int k = L * i + p;
+    const cplx<T> zb = tb[(M - k) % M];  // Z_{M-k}
+    const T Dr = zr[i] + zb.r, Di = zi[i] - zb.i;
+    const cplx<T> S{zr[i] - zb.r, zi[i] + zb.i};
+    const cplx<T> V = cmulc(S, tw[k]);  // e^{-2 pi i k / N} S
+    X[i] = cplx<T>{Dr + V.i, Di - V.r};
+  });
+  row_sync();
+}
+
+// The transform pair for L lanes per row: the two-stage split when Q is a
+// multiple of L, the pair split when L = 2Q.
+template <int N, int L, typename T, class XF>
+__device__ __forceinline__ void c2r_rows(XF X, int p, cplx<T>* tb, const cplx<T>* tw,
+                                         const cplx<T>* tw2, T (&out)[N / L]) {
+  if constexpr (L == N / L)
+    c2r_lanes_split<N, L, T>(X, p, tb, tw, tw2, out);
+  else
+    c2r_lanes<N, L, T>(X, p, tb, tw, tw2, out);
+}
+template <int N, int KM, int L, typename T>
+__device__ __forceinline__ void r2c_rows(const T (&in)[N / L], int p, cplx<T>* tb,
+                                         const cplx<T>* tw, const cplx<T>* tw2,
+                                         cplx<T> (&X)[(KM + L - 1) / L]) {
+  if constexpr (L == N / L)
+    r2c_lanes_split<N, KM, L, T>(in, p, tb, tw, tw2, X);
+  else
+    r2c_lanes<N, KM, L, T>(in, p, tb, tw, tw2, X);
 }
 
 template <int NX, typename T, int W, int MODE, int L>
@@ -170,19 +339,31 @@ __device__ __forceinline__ void tile_body_lanes(const KernelArgs<T>& a, const Cu
   const bool interior = (jr >= 1) && (jr <= n_s - 2);
 
   // LDS: staging rows (dtype T), residual rows (FP64), transpose blocks
-  // (FP64), twiddles (FP64)
+  // (FP64), twiddles e^{2 pi i j / N} and e^{2 pi i m1 p / M} (FP64, then the
+  // same rounded to the state dtype for pass 1)
+  constexpr int RS = lanes_rstride(KM), BS = lanes_bstride(NX, L);
   cplx<double>* r64 = reinterpret_cast<cplx<double>*>(
       reinterpret_cast<char*>(buf) + lanes_stage_bytes(KM, ROWS, int(sizeof(T))));
-  cplx<double>* tbd = r64 + BR * KM + t * M;  // this row's transpose block
-  cplx<double>* tw = r64 + BR * KM + ROWS * M;
+  cplx<double>* tbd = r64 + BR * RS + t * BS;  // this row's transpose block
+  cplx<double>* tw = r64 + BR * RS + ROWS * BS;
+  cplx<double>* tw2 = tw + M;
+  cplx<T>* twT = reinterpret_cast<cplx<T>*>(tw2 + M);
+  cplx<T>* tw2T = twT + M;
 
   const long long base = cd.off + (long long)(j0 - 1) * KM;
   const int sh = int(((base % E) + E) % E);
   __syncthreads();  // the previous tile of a persistent workgroup is done with the LDS
-  for (int j = threadIdx.x; j < NX; j += NT) {
+  for (int j = threadIdx.x; j < M; j += NT) {
     double s, co;
     sincospi(2.0 * j / NX, &s, &co);
     tw[j] = cplx<double>{co, s};
+    twT[j] = cplx<T>{T(co), T(s)};
+  }
+  for (int j = threadIdx.x; j < M; j += NT) {
+    double s, co;
+    sincospi(2.0 * ((j / L) * (j % L)) / M, &s, &co);
+    tw2[j] = cplx<double>{co, s};
+    tw2T[j] = cplx<T>{T(co), T(s)};
   }
   stage_block<cplx<T>, NT, BR * KM + E>(buf, a.in, base, sh, BR * KM + sh,
                                         cd.off + (long long)(j0 > 0 ? j0 - 1 : 0) * KM,
@@ -199,7 +380,7 @@ __device__ __forceinline__ void tile_body_lanes(const KernelArgs<T>& a, const Cu
   cplx<double> S0[KL];
   {
     double v[NS];
-    c2r_lanes<NX, L, double>(
+    c2r_rows<NX, L, double>(
         [&](int k) {
           cplx<double> x{0.0, 0.0};
           if (k < KM) {
@@ -208,7 +389,7 @@ __device__ __forceinline__ void tile_body_lanes(const KernelArgs<T>& a, const Cu
           }
           return x;
         },
-        p, tbd, tw, v);
+        p, tbd, tw, tw2, v);
     if constexpr (MODE != MODE_J) {
       sfor<NS>([&](auto Nn) {
         constexpr int n = Nn;
@@ -219,7 +400,7 @@ __device__ __forceinline__ void tile_body_lanes(const KernelArgs<T>& a, const Cu
       constexpr int n = Nn;
       v[n] = v[n] * v[n];
     });
-    r2c_lanes<NX, KM, L, double>(v, p, tbd, tw, S0);
+    r2c_rows<NX, KM, L, double>(v, p, tbd, tw, tw2, S0);
   }
 
   // ---- residual of the lane's modes (FP64), its row sums ----
@@ -271,20 +452,23 @@ __device__ __forceinline__ void tile_body_lanes(const KernelArgs<T>& a, const Cu
   sfor<KL>([&](auto I) {
     constexpr int i = I;
     const int k = L * i + p;
-    if (k < KM) r64[(t + 1) * KM + k] = R[i];
+    if (k < KM) r64[(t + 1) * RS + k] = R[i];
   });
   for (int i = threadIdx.x; i < 2 * KM; i += NT)
-    r64[(i < KM) ? i : (BR - 2) * KM + i] = cplx<double>{0.0, 0.0};
+    r64[(i < KM) ? i : (BR - 1) * RS + i - KM] = cplx<double>{0.0, 0.0};
   __syncthreads();
 
   // ---- pass 1 in the state dtype: S = r2c(u * c2r(i q r_hat / (2 N_x))) = Q_hat ----
   cplx<T> S[KL];
   {
-    const cplx<double>* rme = r64 + (t + 1) * KM;
+    const cplx<double>* rme = r64 + (t + 1) * RS;
     const T qY1 = T(cd.q1 / (2.0 * NX));
-    cplx<T>* tbt = reinterpret_cast<cplx<T>*>(tbd);
+    // the row's block in the state dtype: the pair-split layout packs the
+    // FP32 blocks at half the FP64 stride (an odd multiple of 128 bytes)
+    constexpr int BST = (L * L == NX) ? BS : BS * int(sizeof(cplx<double>) / sizeof(cplx<T>));
+    cplx<T>* tbt = reinterpret_cast<cplx<T>*>(r64 + BR * RS) + t * BST;
     T v[NS];
-    c2r_lanes<NX, L, T>(
+    c2r_rows<NX, L, T>(
         [&](int k) {
           cplx<T> x{T(0), T(0)};
           if (k < KM) {
@@ -294,12 +478,12 @@ __device__ __forceinline__ void tile_body_lanes(const KernelArgs<T>& a, const Cu
           }
           return x;
         },
-        p, tbt, tw, v);
+        p, tbt, twT, tw2T, v);
     sfor<NS>([&](auto Nn) {
       constexpr int n = Nn;
       v[n] = u[n] * v[n];
     });
-    r2c_lanes<NX, KM, L, T>(v, p, tbt, tw, S);
+    r2c_rows<NX, KM, L, T>(v, p, tbt, twT, tw2T, S);
   }
 
   // ---- L^dagger r = g (r_{j+1} - r_{j-1}) / (2 dsigma) + Q_hat + A r_hat ----
@@ -313,7 +497,7 @@ __device__ __forceinline__ void tile_body_lanes(const KernelArgs<T>& a, const Cu
       const int k = L * i + p;
       D[i] = cplx<T>{T(0), T(0)};
       if (k < KM) {
-        const cplx<double> rm = r64[t * KM + k], rp = r64[(t + 2) * KM + k];
+        const cplx<double> rm = r64[t * RS + k], rp = r64[(t + 2) * RS + k];
         const double qk = double(k) * q1;
         const double q2 = qk * qk;
         const double Ak = fmaT(-q2, q2, q2);

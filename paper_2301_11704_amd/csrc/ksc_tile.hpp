@@ -510,13 +510,24 @@ __device__ __forceinline__ void tile_body(const KernelArgs<T>& a, const CurveDev
   }
 }
 
+// Lanes per row of the FP32 N_x = 256 tile kernel (ksc_lanes.hpp): 16 lanes
+// give a 8190-row curve 2048 waves, two per SIMD.
+constexpr int kLanesF32N256 = 16;
+
 // Lanes per row: one whole row per lane while its transform fits the
 // registers (N_x reals of the field kept for the adjoint plus N_x of
 // transform work space), else a lane pair per row.
 template <int NX, typename T>
 constexpr int lanes_per_row() {
-  if (sizeof(T) == 4 && NX == 256) return 8;  // ksc_lanes.hpp
+  if (sizeof(T) == 4 && NX == 256) return kLanesF32N256;
   return (NX * int(sizeof(T)) > 512) ? 2 : 1;
+}
+
+// Waves per SIMD that a tile kernel is compiled for: the 16-lane kernel keeps
+// two resident (at most 256 VGPRs each), the others one.
+template <int NX, typename T>
+constexpr int tile_waves_per_simd() {
+  return (lanes_per_row<NX, T>() * lanes_per_row<NX, T>() == NX) ? 2 : 1;
 }
 
 // The same evaluation with two lanes per row (lane 2r + p holds modes

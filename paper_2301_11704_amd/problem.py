@@ -73,14 +73,18 @@ class Problem:
         self.ds = ds
         self.dtype = dtype
         self.device = torch.device(device)
+        self._dev_index = self.device.index if self.device.index is not None \
+            else torch.cuda.current_device()
         arr = (_lib.CurveDescC * len(self.curves))(*[c.to_c() for c in self.curves])
         h = ctypes.c_void_p()
         dt = _lib.KSC_F64 if dtype == torch.float64 else _lib.KSC_F32
         opts = _lib.OptionsC(dt, spaces[space], dss[ds], 0)
         with torch.cuda.device(self.device):
-            check(lib().ksc_create_opts(arr, len(self.curves), ctypes.byref(opts), self._stream(),
+            s0 = self._stream()
+            check(lib().ksc_create_opts(arr, len(self.curves), ctypes.byref(opts), s0,
                                         ctypes.byref(h)))
         self._h = h
+        self._bound_stream = s0  # the stream the library launches on
         L = lib()
         self.numel = int(L.ksc_state_numel(h))
         self.phys_numel = int(L.ksc_phys_numel(h))
@@ -90,10 +94,14 @@ class Problem:
 
     # -- plumbing ----------------------------------------------------------
     def _stream(self) -> int:
-        return torch.cuda.current_stream(self.device).cuda_stream
+        return torch._C._cuda_getCurrentRawStream(self._dev_index)
 
     def _sync_stream(self):
-        check(lib().ksc_set_stream(self._h, self._stream()))
+        # rebind only when torch's current stream changed since the last call
+        s = self._stream()
+        if s != self._bound_stream:
+            check(lib().ksc_set_stream(self._h, s))
+            self._bound_stream = s
 
     def close(self):
         if getattr(self, "_h", None):
@@ -111,7 +119,7 @@ class Problem:
         return len(self.curves)
 
     def _check_state(self, t: torch.Tensor, name="state"):
-        if not isinstance(t, torch.Tensor) or t.device.type != "cuda":
+        if not isinstance(t, torch.Tensor) or not t.is_cuda:
             raise TypeError(f"{name} must be a CUDA (HIP) tensor")
         if t.dtype != self.dtype or t.numel() != self.numel or not t.is_contiguous():
             raise ValueError(f"{name} must be a contiguous {self.dtype} tensor of {self.numel} scalars")
@@ -191,7 +199,8 @@ class Problem:
         if scale is not None:
             if scale.dtype != torch.float64 or scale.numel() != self.n_curves:
                 raise ValueError("scale must be an FP64 tensor of n_curves entries")
-            scale = scale.contiguous()
+            if not scale.is_contiguous():
+                scale = scale.contiguous()
         J2 = self._f64(self.n_curves) if want_J2 else None
         self._sync_stream()
         check(lib().ksc_eval_grad(self._h, _ptr(state), _ptr(grad), _ptr(J2), _ptr(scale)))
