@@ -68,7 +68,7 @@ def flops_per_row_odd(n_x: int) -> float:
 # a traffic summary under profiles/ applies only while their hash is the one
 # recorded there.
 KERNEL_SOURCES = {
-    "full": ("ksc_tile.hpp", "ksc_fft.hpp", "ksc_fused.hip", "ksc_launch.hpp"),
+    "full": ("ksc_tile.hpp", "ksc_fft.hpp", "ksc_lanes.hpp", "ksc_fused.hip", "ksc_launch.hpp"),
     "odd": ("ksc_tile.hpp", "ksc_fft.hpp", "ksc_sym.hpp", "ksc_odd.hpp", "ksc_odd.hip",
             "ksc_launch_odd.hpp"),
 }

@@ -378,8 +378,7 @@ size_t lds_for(const ksc_problem* p, int W, int nx) {
   const size_t cs = 2 * p->esize();
   // plus the samples of u that each lane parks in LDS between the passes
   // (ksc::u_stash of the tile kernels)
-  const size_t stash = (p->esize() == 4) ? size_t(64 * W) * ksc::u_stash<128, float>() * 4 : 0;
-  const size_t park = (nx == 128) ? stash : 0;
+  const size_t park = size_t(64 * W) * ksc::u_stash_n(nx, int(p->esize())) * p->esize();
   return (size_t(rows_per_tile(p, W, nx) + 2) * modes_of(nx) + 2) * cs + park;
 }
 // Largest staging buffer over the grid sizes of the problem (one launch may
@@ -1213,8 +1212,7 @@ ksc_status eval_J_noalloc_t(const ksc_curve_desc& d, int n_curves, const void* s
   size_t lds = 0;
   for (int w : {4, 2, 1}) {
     const size_t rows = size_t(64 * w / lanes) + 2;
-    const size_t park = (sizeof(T) == 4 && d.n_x == 128)
-                            ? size_t(64 * w) * ksc::u_stash<128, float>() * 4 : 0;
+    const size_t park = size_t(64 * w) * ksc::u_stash_n(d.n_x, int(sizeof(T))) * sizeof(T);
     const size_t b = (lanes > 2)
                          ? size_t(ksc::lanes_lds_bytes(d.n_x, km, 64 * w / lanes, lanes, int(sizeof(T))))
                          : (rows * km + 2) * 2 * sizeof(T) + park;

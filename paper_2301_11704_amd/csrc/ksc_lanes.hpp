@@ -1,32 +1,28 @@
 // Rows split over L lanes: the fused tile evaluation for grids whose row is
 // too wide for one lane (N_x = 256 in FP32), with every row's transforms
-// spread over L consecutive lanes so that a long curve fills the chip.
+// spread over L = sqrt(N_x) consecutive lanes so that a long curve fills the
+// chip (a 8190-row curve at N_x = 256 gets 2048 waves, two per SIMD).
 //
 // Layout of one row over its L lanes (lane p = 0..L-1 of the row's group),
-// with the half-length trick z_m = x_{2m} + i x_{2m+1}, m < M = N/2 = L Q:
+// with the half-length trick z_m = x_{2m} + i x_{2m+1}, m < M = N/2 = L Q,
+// L = 2Q:
 //   spectrum side: lane p holds the coefficients k = L k1 + p, k1 < Q;
-//   sample side:   lane p holds z_m for m = m1 + Q m2 with m1 = p Q/L + j,
-//                  j < Q/L, m2 < L, at index j L + m2.
-// The M-point DFT splits as  z_{m1 + Q m2} = sum_p w_L^{m2 p} w_M^{m1 p}
-// sum_{k1} w_Q^{m1 k1} Z_{L k1 + p}:  a Q-point FFT in each lane, a twiddle,
-// a transpose of the row's L x Q block through LDS, and Q/L L-point FFTs in
-// each lane (the forward transform runs the same steps in reverse).  The
-// transpose moves data through LDS instead of cross-lane butterflies, so the
-// arithmetic is that of the single-lane transform plus one twiddle per point.
+//   sample side:   lane p = 2 m1 + h holds z_m for m = m1 + Q (j + Q h),
+//                  j < Q.
+// The M-point DFT splits as z_{m1 + Q m2} = sum_p w_L^{m2 p} w_M^{m1 p}
+// sum_{k1} w_Q^{m1 k1} Z_{L k1 + p}: a Q-point FFT in each lane, a twiddle
+// w_M^{m1 p}, a transpose of the row's Q x L block through LDS that gives
+// lane (m1, h) the entries p = 2 pp + h of line m1, a Q-point FFT over pp in
+// each lane (the even / odd half of the L-point DFT over p), and one radix-2
+// step across the lane pair, E + w_L^j O and E - w_L^j O, with the partner's
+// values from a DPP lane swap.  The forward transform runs the same steps in
+// reverse.
 //
-// With L = 2Q (more lanes than points per lane) the L-point stage over p runs
-// in the lane pairs (m1, h), m1 < Q, h = 0 / 1 holding the even / odd p of
-// that m1: a Q-point FFT in each lane, then one radix-2 step across the pair
-// (a DPP lane swap), E + w_L^j O and E - w_L^j O; a lane then holds z_m for
-// m = m1 + Q (j + Q h), j < Q.  The forward transform mirrors it.
-//
-// LDS banks: in the transpose block, entry (m1, q) sits in column
-// (q + m1 / (Q/L)) mod L of row m1, so that the L lanes of a row touch L
-// different columns both when each writes its own q and when each reads the
-// L entries of its own m1 (a plain layout puts those reads Q/L * L entries
-// apart, on the same banks).  Row blocks and residual rows are padded to an
-// odd multiple of 128 bytes so that neighbouring rows use the other half of
-// the banks.
+// LDS banks: block entry (m1, q) sits at m1 (L + 2) + q.  The L lanes of a
+// row then touch 16-byte groups on distinct banks both when each writes its
+// own q of a line and when the pairs read their half-lines; in the state
+// dtype the blocks of neighbouring rows are an odd multiple of 128 bytes
+// apart, and so are the FP64 residual rows.
 //
 // Pass 0 (u = c2r(u_hat), N_hat = r2c(u^2), the residual) runs in FP64 as in
 // the one-lane kernel; the residual rows are exchanged between neighbouring
@@ -38,18 +34,16 @@
 
 namespace ksc {
 
-// LDS footprint (bytes) of the L-lane tile of W waves: staging rows (state
-// dtype), residual rows (FP64), the transpose blocks (FP64, one row of M
-// complex values per tile row) and the twiddle table e^{2 pi i j / N} (FP64).
+// LDS footprint (bytes) of the L-lane tile of R rows: staging rows (state
+// dtype), residual rows (FP64), the transpose blocks (FP64, one per tile
+// row) and the twiddle tables.
 constexpr int lanes_stage_bytes(int KM, int R, int esize) {
   return ((((R + 2) * KM + 2) * 2 * esize) + 15) / 16 * 16;
 }
 // Padded strides (complex FP64 entries): residual rows and transpose blocks
-// (the pair-split layout pads each of its Q lines of L entries by 2).
+// (Q lines of L entries, each padded by 2).
 constexpr int lanes_rstride(int KM) { return (KM + 7) / 16 * 16 + 8; }
-constexpr int lanes_bstride(int NX, int L) {
-  return (L * L == NX) ? (NX / 2 / L) * (L + 2) : NX / 2 + 8;
-}
+constexpr int lanes_bstride(int NX, int L) { return (NX / 2 / L) * (L + 2); }
 // Twiddle tables: e^{2 pi i k / N} for k < N/2 and e^{2 pi i m1 p / M}, in
 // FP64 and in the state dtype.
 constexpr int lanes_lds_bytes(int NX, int KM, int R, int L, int esize) {
@@ -81,109 +75,9 @@ __device__ __forceinline__ void row_sync() {
 
 // Band-limited spectrum -> this lane's samples (layout above).  X(k) returns
 // coefficient k (0 for k > K; Im of mode 0 ignored); tb: the row's transpose
-// block in LDS (M complex of type T); tw: e^{2 pi i j / N}, j < N/2, and tw2:
-// e^{2 pi i m1 p / M} at m1 L + p, both in LDS in the arithmetic type.  All L
-// lanes of the row call it together.
-template <int N, int L, typename T, class XF>
-__device__ __forceinline__ void c2r_lanes(XF X, int p, cplx<T>* tb, const cplx<T>* tw,
-                                          const cplx<T>* tw2, T (&out)[N / L]) {
-  using namespace lanes_detail;
-  constexpr int M = N / 2, Q = M / L, QL = Q / L;
-  static_assert(Q % L == 0, "Q must be a multiple of L");
-  static_assert(64 % L == 0, "a row's lanes must sit in one wave");
-  T zr[Q], zi[Q];
-  sfor<Q>([&](auto K1) {
-    constexpr int k1 = K1;
-    const int k = L * k1 + p;
-    const cplx<T> a = X(k);
-    cplx<T> b = X(M - k);  // zero for k = 0 (coefficient M is above K)
-    b.i = -b.i;            // conj
-    const cplx<T> E{a.r + b.r, a.i + b.i};
-    const cplx<T> O = cmul(cplx<T>{a.r - b.r, a.i - b.i}, tw[k]);
-    zr[k1] = E.r - O.i;  // Z = E + i O
-    zi[k1] = E.i + O.r;
-  });
-  fft_c<Q, +1, T>(zr, zi);
-  sfor<Q>([&](auto M1) {
-    constexpr int m1 = M1;
-    const cplx<T> y = cmul(cplx<T>{zr[m1], zi[m1]}, tw2[m1 * L + p]);
-    tb[m1 * L + ((p + m1 / QL) & (L - 1))] = y;
-  });
-  row_sync();
-  sfor<QL>([&](auto J) {
-    constexpr int j = J;
-    const int m1 = p * QL + j;
-    T tr[L], ti[L];
-    sfor<L>([&](auto Qq) {
-      constexpr int q = Qq;
-      const cplx<T> v = tb[m1 * L + ((q + p) & (L - 1))];
-      tr[q] = v.r;
-      ti[q] = v.i;
-    });
-    fft_c<L, +1, T>(tr, ti);
-    sfor<L>([&](auto M2) {
-      constexpr int m2 = M2;
-      out[2 * (j * L + m2)] = tr[m2];
-      out[2 * (j * L + m2) + 1] = ti[m2];
-    });
-  });
-  row_sync();
-}
-
-// This lane's samples -> its kept coefficients, unnormalized and doubled:
-//   X_k = 2 sum_n x_n e^{-2 pi i k n / N} for k = L i + p <= K (X[i]).
-template <int N, int KM, int L, typename T>
-__device__ __forceinline__ void r2c_lanes(const T (&in)[N / L], int p, cplx<T>* tb,
-                                          const cplx<T>* tw, const cplx<T>* tw2,
-                                          cplx<T> (&X)[(KM + L - 1) / L]) {
-  using namespace lanes_detail;
-  constexpr int M = N / 2, Q = M / L, QL = Q / L, KL = (KM + L - 1) / L;
-  sfor<QL>([&](auto J) {
-    constexpr int j = J;
-    const int m1 = p * QL + j;
-    T tr[L], ti[L];
-    sfor<L>([&](auto M2) {
-      constexpr int m2 = M2;
-      tr[m2] = in[2 * (j * L + m2)];
-      ti[m2] = in[2 * (j * L + m2) + 1];
-    });
-    fft_c<L, -1, T>(tr, ti);
-    sfor<L>([&](auto Qq) {
-      constexpr int q = Qq;
-      tb[m1 * L + ((q + p) & (L - 1))] = cplx<T>{tr[q], ti[q]};
-    });
-  });
-  row_sync();
-  T zr[Q], zi[Q];
-  sfor<Q>([&](auto M1) {
-    constexpr int m1 = M1;
-    const cplx<T> w = cmulc(tb[m1 * L + ((p + m1 / QL) & (L - 1))], tw2[m1 * L + p]);
-    zr[m1] = w.r;
-    zi[m1] = w.i;
-  });
-  row_sync();
-  fft_c<Q, -1, T>(zr, zi);  // Z_{L k1 + p} at k1
-  sfor<Q>([&](auto K1) {
-    constexpr int k1 = K1;
-    tb[L * k1 + p] = cplx<T>{zr[k1], zi[k1]};
-  });
-  row_sync();
-  sfor<KL>([&](auto I) {
-    constexpr int i = I;
-    const int k = L * i + p;
-    const cplx<T> zb = tb[(M - k) % M];  // Z_{M-k}
-    const T Dr = zr[i] + zb.r, Di = zi[i] - zb.i;
-    const cplx<T> S{zr[i] - zb.r, zi[i] + zb.i};
-    const cplx<T> V = cmulc(S, tw[k]);  // e^{-2 pi i k / N} S
-    X[i] = cplx<T>{Dr + V.i, Di - V.r};
-  });
-  row_sync();
-}
-
-// L = 2Q: band-limited spectrum -> this lane's samples (z_m at m = m1 + Q (j
-// + Q h), m1 = p / 2, h = p mod 2, j < Q); block entry (m1, q) at
-// m1 (L + 2) + q, which puts the 16 entries that a row's lanes read at once
-// on 16 different 16-byte bank groups.
+// block in LDS; tw: e^{2 pi i k / N}, k < N/2, and tw2: e^{2 pi i m1 p / M}
+// at m1 L + p, both in LDS in the arithmetic type.  All L lanes of the row
+// call it together.
 template <int N, int L, typename T, class XF>
 __device__ __forceinline__ void c2r_lanes_split(XF X, int p, cplx<T>* tb, const cplx<T>* tw,
                                                 const cplx<T>* tw2, T (&out)[N / L]) {
@@ -238,8 +132,8 @@ __device__ __forceinline__ void c2r_lanes_split(XF X, int p, cplx<T>* tb, const 
   });
 }
 
-// L = 2Q: this lane's samples (layout of c2r_lanes_split) -> its kept
-// coefficients, unnormalized and doubled (as r2c_lanes).
+// This lane's samples -> its kept coefficients, unnormalized and doubled:
+//   X_k = 2 sum_n x_n e^{-2 pi i k n / N} for k = L i + p <= K (X[i]).
 template <int N, int KM, int L, typename T>
 __device__ __forceinline__ void r2c_lanes_split(const T (&in)[N / L], int p, cplx<T>* tb,
                                                 const cplx<T>* tw, const cplx<T>* tw2,
@@ -300,26 +194,6 @@ __device__ __forceinline__ void r2c_lanes_split(const T (&in)[N / L], int p, cpl
   row_sync();
 }
 
-// The transform pair for L lanes per row: the two-stage split when Q is a
-// multiple of L, the pair split when L = 2Q.
-template <int N, int L, typename T, class XF>
-__device__ __forceinline__ void c2r_rows(XF X, int p, cplx<T>* tb, const cplx<T>* tw,
-                                         const cplx<T>* tw2, T (&out)[N / L]) {
-  if constexpr (L == N / L)
-    c2r_lanes_split<N, L, T>(X, p, tb, tw, tw2, out);
-  else
-    c2r_lanes<N, L, T>(X, p, tb, tw, tw2, out);
-}
-template <int N, int KM, int L, typename T>
-__device__ __forceinline__ void r2c_rows(const T (&in)[N / L], int p, cplx<T>* tb,
-                                         const cplx<T>* tw, const cplx<T>* tw2,
-                                         cplx<T> (&X)[(KM + L - 1) / L]) {
-  if constexpr (L == N / L)
-    r2c_lanes_split<N, KM, L, T>(in, p, tb, tw, tw2, X);
-  else
-    r2c_lanes<N, KM, L, T>(in, p, tb, tw, tw2, X);
-}
-
 template <int NX, typename T, int W, int MODE, int L>
 __device__ __forceinline__ void tile_body_lanes(const KernelArgs<T>& a, const CurveDev& cd, int c,
                                                 int j0, int tile, cplx<T>* buf) {
@@ -332,6 +206,7 @@ __device__ __forceinline__ void tile_body_lanes(const KernelArgs<T>& a, const Cu
   constexpr int E = 16 / int(sizeof(cplx<T>));
   constexpr int M = NX / 2;
   constexpr int NS = NX / L;            // samples per lane
+  static_assert(L * L == NX, "L = sqrt(N_x) lanes per row");
   const int t = threadIdx.x / L;        // row within the tile
   const int p = threadIdx.x % L;
   const int n_s = cd.n_s;
@@ -380,7 +255,7 @@ __device__ __forceinline__ void tile_body_lanes(const KernelArgs<T>& a, const Cu
   cplx<double> S0[KL];
   {
     double v[NS];
-    c2r_rows<NX, L, double>(
+    c2r_lanes_split<NX, L, double>(
         [&](int k) {
           cplx<double> x{0.0, 0.0};
           if (k < KM) {
@@ -400,7 +275,7 @@ __device__ __forceinline__ void tile_body_lanes(const KernelArgs<T>& a, const Cu
       constexpr int n = Nn;
       v[n] = v[n] * v[n];
     });
-    r2c_rows<NX, KM, L, double>(v, p, tbd, tw, tw2, S0);
+    r2c_lanes_split<NX, KM, L, double>(v, p, tbd, tw, tw2, S0);
   }
 
   // ---- residual of the lane's modes (FP64), its row sums ----
@@ -463,12 +338,11 @@ __device__ __forceinline__ void tile_body_lanes(const KernelArgs<T>& a, const Cu
   {
     const cplx<double>* rme = r64 + (t + 1) * RS;
     const T qY1 = T(cd.q1 / (2.0 * NX));
-    // the row's block in the state dtype: the pair-split layout packs the
-    // FP32 blocks at half the FP64 stride (an odd multiple of 128 bytes)
-    constexpr int BST = (L * L == NX) ? BS : BS * int(sizeof(cplx<double>) / sizeof(cplx<T>));
-    cplx<T>* tbt = reinterpret_cast<cplx<T>*>(r64 + BR * RS) + t * BST;
+    // the row's block in the state dtype, packed at BS entries of that type
+    // (an odd multiple of 128 bytes in FP32)
+    cplx<T>* tbt = reinterpret_cast<cplx<T>*>(r64 + BR * RS) + t * BS;
     T v[NS];
-    c2r_rows<NX, L, T>(
+    c2r_lanes_split<NX, L, T>(
         [&](int k) {
           cplx<T> x{T(0), T(0)};
           if (k < KM) {
@@ -483,7 +357,7 @@ __device__ __forceinline__ void tile_body_lanes(const KernelArgs<T>& a, const Cu
       constexpr int n = Nn;
       v[n] = u[n] * v[n];
     });
-    r2c_rows<NX, KM, L, T>(v, p, tbt, twT, tw2T, S);
+    r2c_lanes_split<NX, KM, L, T>(v, p, tbt, twT, tw2T, S);
   }
 
   // ---- L^dagger r = g (r_{j+1} - r_{j-1}) / (2 dsigma) + Q_hat + A r_hat ----

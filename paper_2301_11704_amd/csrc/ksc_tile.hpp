@@ -254,11 +254,14 @@ __device__ __forceinline__ void flush_block(V* __restrict__ gout, const V* __res
 // Samples of the physical field u that a lane parks in LDS between the two
 // passes of the gradient (the rest stay in registers).  Only where pass 0's
 // FP64 transform work space would not fit next to the whole field: N_x = 128
-// with one FP32 row per lane.  The host adds lanes * u_stash * sizeof(T)
-// bytes to the staging buffer's LDS.
+// with one FP32 row per lane (64 of its 128 samples).  The host adds
+// lanes * u_stash * esize bytes to the staging buffer's LDS.
+constexpr int u_stash_n(int nx, int esize) {
+  return (nx == 128 && esize == 4) ? 64 : 0;
+}
 template <int NX, typename T>
 constexpr int u_stash() {
-  return (sizeof(T) == 4 && NX == 128) ? 64 : 0;
+  return u_stash_n(NX, int(sizeof(T)));
 }
 
 template <int NX, typename T, int W, int MODE>
@@ -532,6 +535,7 @@ constexpr int tile_waves_per_simd() {
 
 // The same evaluation with two lanes per row (lane 2r + p holds modes
 // k = 2i + p and samples [p N/2, (p+1) N/2) of row j0 + r): a tile is 32W rows.
+// It serves FP64 rows of N_x >= 128, so both passes run in the state dtype.
 template <int NX, typename T, int W, int MODE>
 __device__ __forceinline__ void tile_body2(const KernelArgs<T>& a, const CurveDev& cd, int c,
                                            int j0, int tile, cplx<T>* buf) {
@@ -557,6 +561,7 @@ __device__ __forceinline__ void tile_body2(const KernelArgs<T>& a, const CurveDe
                                   cd.off + (long long)(j0 > 0 ? j0 - 1 : 0) * KM,
                                   cd.off + (long long)min(n_s, j0 + ROWS + 1) * KM);
   __syncthreads();
+  static_assert(sizeof(T) == 8, "lane pairs serve FP64 rows");
   cplx<T>* __restrict__ rows = buf + sh;
   // this lane's entry i of a row is mode 2i + p; the last entry of lane 1 may
   // lie past K (odd KM): it reads as zero and is never written
@@ -569,36 +574,15 @@ __device__ __forceinline__ void tile_body2(const KernelArgs<T>& a, const CurveDe
   constexpr int CH = 7;
   constexpr int NCH = (KH + CH - 1) / CH;
 
-  // ---- pass 0 in FP64 whatever the state dtype (see tile_body) ----
   cplx<T> In[KH];
   sfor<KH>([&](auto Ii) {
     constexpr int i = Ii;
     In[i] = ok(i) ? rows[(t + 1) * KM + 2 * i + p] : cplx<T>{T(0), T(0)};
   });
-  constexpr int US = (MODE == MODE_J) ? 0 : u_stash<NX, T>();
-  T u[MODE == MODE_J ? 1 : NH - US];
-  T* __restrict__ ust = reinterpret_cast<T*>(buf + (BR * KM + E)) + threadIdx.x;  // [US][NT]
-  cplx<double> S0[KH];
-  {
-    double v[NH];
-    spec_to_phys_pair<NX, KH, double, T>(In, double(p), v);
-    if constexpr (MODE != MODE_J) {
-      sfor<NH>([&](auto Nn) {
-        constexpr int n = Nn;
-        if constexpr (n < US)
-          ust[n * NT] = T(v[n]);
-        else
-          u[n - US] = T(v[n]);
-      });
-    }
-    sfor<NH>([&](auto Nn) {
-      constexpr int n = Nn;
-      v[n] = v[n] * v[n];
-    });
-    phys_to_spec2_pair<NX, KH, double>(v, double(p), S0);
-  }
+  T u[MODE == MODE_J ? 1 : NH];
   cplx<T> R[KH];
-  {
+  // r_hat from S0 = r2c(u^2), the cost partials
+  auto residual = [&](const cplx<double>(&S0)[KH]) {
     double rowR0 = 0.0, rowR = 0.0, rowD0 = 0.0, rowD = 0.0;
     double q1_r = cd.q1, qN1_r = cd.q1 / (4.0 * NX), pf_r = double(p), cs_r = double(csj);
     __asm__ volatile("" : "+v"(q1_r), "+v"(qN1_r), "+v"(pf_r), "+v"(cs_r));
@@ -671,9 +655,10 @@ __device__ __forceinline__ void tile_body2(const KernelArgs<T>& a, const CurveDe
       }
     }
     store_wave_partials<W, (MODE == MODE_J) ? 3 : 1>(pj, pn, pd, tile_partials(a, cd, c, tile, W));
-  }
-  cplx<T> S[KH];
-  if constexpr (MODE != MODE_J) {
+  };
+  // the residual rows to the staging buffer (for the neighbours' d/ds) and
+  // In = i q r_hat / (2 N_x), the input of pass 1
+  auto exchange = [&]() {
     __syncthreads();
     T qY1_r = qY1, pf_y = pf;
     __asm__ volatile("" : "+v"(qY1_r), "+v"(pf_y));
@@ -686,17 +671,41 @@ __device__ __forceinline__ void tile_body2(const KernelArgs<T>& a, const CurveDe
     for (int i = threadIdx.x; i < 2 * KM; i += NT)
       rows[(i < KM) ? i : (BR - 2) * KM + i] = cplx<T>{T(0), T(0)};
     __syncthreads();
-    // ---- pass 1 in the state dtype: S = r2c(u * c2r(i q r_hat / (2 N_x))) ----
-    T v[NH];
-    spec_to_phys_pair<NX, KH, T>(In, pf, v);
-    sfor<NH>([&](auto Nn) {
-      constexpr int n = Nn;
-      if constexpr (n < US)
-        v[n] = ust[n * NT] * v[n];
-      else
-        v[n] = u[n - US] * v[n];
-    });
-    phys_to_spec2_pair<NX, KH, T>(v, pf, S);
+  };
+  cplx<T> S[KH];
+  {
+    // both passes through one copy of the transforms (a runtime loop of two
+    // iterations keeps the code, and the register allocation, of one pass)
+    constexpr int NPASS = (MODE == MODE_J) ? 1 : 2;
+#pragma clang loop unroll(disable)
+    for (int pass = 0; pass < NPASS; ++pass) {
+      {
+        T v[NH];
+        spec_to_phys_pair<NX, KH, T>(In, pf, v);
+        if constexpr (MODE == MODE_J) {
+          sfor<NH>([&](auto Nn) {
+            constexpr int n = Nn;
+            v[n] = v[n] * v[n];
+          });
+        } else {
+          if (pass == 0) {
+            sfor<NH>([&](auto Nn) {
+              constexpr int n = Nn;
+              u[n] = v[n];
+            });
+          }
+          sfor<NH>([&](auto Nn) {
+            constexpr int n = Nn;
+            v[n] = u[n] * v[n];
+          });
+        }
+        phys_to_spec2_pair<NX, KH, T>(v, pf, S);
+      }
+      if (pass == 0) {
+        residual(S);
+        if constexpr (MODE != MODE_J) exchange();
+      }
+    }
   }
 
   if constexpr (MODE != MODE_J) {

@@ -122,8 +122,10 @@ def descend_to(backend, dtau: float, J_target: float = 1e-8, max_steps: int = 10
     be a promoted (FP64) one holding the final state.  progress(log, J) is
     called after every accepted chunk with the per-curve J.  momentum > 0
     (implicit-in-s scheme) turns on the library's heavy-ball momentum from
-    the FP64 switch on, for the slow final approach; the FP32 phase, far from
-    the minimum, runs the plain steps."""
+    the second FP64 chunk on, for the slow final approach; the FP32 phase, far
+    from the minimum, runs the plain steps.  A chunk whose cost rose with the
+    momentum on is redone with plain steps at the same dtau, and the momentum
+    resumes after it; a rise without momentum halves dtau."""
     every = max(1, int(every))
     chunk = int(chunk or every)
     chunk = max(every, (chunk // every) * every)
@@ -160,6 +162,13 @@ def descend_to(backend, dtau: float, J_target: float = 1e-8, max_steps: int = 10
         trace_bad = ~np.all(np.isfinite(tr[:, active]), axis=0) if tr.size else np.zeros(active.sum(), bool)
         if np.any(rose & active) or np.any(trace_bad):
             backend.restore(last_good)
+            if momentum_on:
+                # the heavy ball overshot: redo the chunk with plain steps at
+                # the same dtau (the momentum comes back after it)
+                backend.set_momentum(0.0)
+                momentum_on = False
+                log.events.append((log.steps, "J rose with momentum; rollback, plain chunk"))
+                continue
             dtau *= 0.5
             log.events.append((log.steps, f"J rose or non-finite; rollback, dtau -> {dtau:.3g}"))
             if dtau < min_dtau:

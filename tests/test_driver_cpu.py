@@ -135,3 +135,59 @@ def test_checkpoint_resume_is_bitwise(tmp_path):
                           fp64_finish=False, checkpoint=ck, resume=True)
     assert log2.steps == 40
     assert np.array_equal(b2.snapshot(), b_full.snapshot())
+
+
+class _MomentumBackend:
+    """A scripted backend: J falls by 10% per chunk, except that the first
+    chunk run with the momentum on makes it rise (an overshoot)."""
+
+    dtype = "f64"
+
+    def __init__(self):
+        self.J = np.array([1.0])
+        self.beta = 0.0
+        self.momentum_chunks = 0
+        self.betas = []
+
+    def n_curves(self):
+        return 1
+
+    def run(self, n_steps, dtau, every):
+        self.betas.append(self.beta)
+        if self.beta > 0:
+            self.momentum_chunks += 1
+            self.J = self.J * (3.0 if self.momentum_chunks == 1 else 0.5)
+        else:
+            self.J = self.J * 0.9
+        return np.tile(self.J ** 2, (max(1, n_steps // every), 1))
+
+    def J2(self):
+        return self.J ** 2
+
+    def set_active(self, mask):
+        pass
+
+    def snapshot(self):
+        return self.J.copy()
+
+    def restore(self, arr):
+        self.J = arr.copy()
+
+    def set_momentum(self, beta):
+        self.beta = beta
+
+
+def test_rise_with_momentum_redoes_the_chunk_without_it():
+    """With the momentum on, a rising chunk is rolled back and redone with
+    plain steps at the same dtau; the momentum then resumes (and here
+    converges); dtau is never halved."""
+    b = _MomentumBackend()
+    _, log = descend_to(b, dtau=0.05, J_target=1e-3, max_steps=300, every=10, chunk=10,
+                        momentum=0.9)
+    msgs = [e[1] for e in log.events]
+    assert "J rose with momentum; rollback, plain chunk" in msgs
+    assert not any("dtau ->" in m for m in msgs)
+    assert log.dtau == 0.05 and log.converged.all()
+    # a plain chunk, the overshooting momentum chunk, its plain redo, then
+    # momentum to the end
+    assert b.betas[:4] == [0.0, 0.9, 0.0, 0.9] and set(b.betas[3:]) == {0.9}
