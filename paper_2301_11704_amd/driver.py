@@ -334,8 +334,8 @@ def main(argv=None):
         if log.Jarc_history and log.Jarc_history[-1][0] == log.steps:
             arc = " J_arc " + np.array2string(log.Jarc_history[-1][1], precision=3)
         print(f"step {log.steps:9d} tau {log.tau:10.3f} {log.dtype} dtau {log.dtau:.2e} "
-              f"J max {np.max(J):.3e} min {np.min(J):.3e}{arc}"
-              f" wall {time.time() - t0:7.1f}s", flush=True)
+              f"J max {np.max(J):.3e} min {np.min(J):.3e} below target {int(np.sum(J < args.target))}"
+              f"{arc} wall {time.time() - t0:7.1f}s", flush=True)
 
     b2, log = descend_to(b, dtau=args.dtau, J_target=args.target, max_steps=args.max_steps,
                          every=args.every, chunk=args.chunk, switch_J=args.switch,
