@@ -78,7 +78,8 @@ CASES = [
     (131, 128, "rational", 40.0),
     (70, 256, "rational", 40.0),
     (300, 8, "finite", 2.0),
-    # two lanes per row (N_x = 256, and N_x = 128 in FP64): several 32W-row tiles
+    # rows split over lanes (16 per row at N_x = 256 in FP32: 4W-row tiles; a
+    # lane pair per row at N_x >= 128 in FP64: 32W-row tiles): several tiles
     (300, 256, "finite", 4.0),
     (520, 128, "finite", 6.0),
 ]
