@@ -3,9 +3,11 @@ whole linear part of the adjoint flow implicit, banded solves along s) against
 the FP64 oracle's ``step_implicit_s`` on the same seeded inputs.
 
 Tolerances: FP32 1e-5 and FP64 1e-12 relative to the state (as for the
-paper's step); the increment u_next - u itself is also checked, to 1e-3
-(FP32: the step's input gradient carries FP32 rounding of the whole fused
-evaluation) and 1e-10 (FP64) of its size."""
+paper's step); the increment u_next - u itself is also checked element by
+element, to 1e-5 (FP32) and 1e-10 (FP64) of its largest entry, beyond the
+half ulp by which a stored FP32 state necessarily misses the exact one (with
+a small step the increment is a few ulps of the state, so its FP32 rounding
+alone would otherwise be a large fraction of it)."""
 import numpy as np
 import pytest
 
@@ -18,7 +20,7 @@ torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
 
 TOL = {np.float32: 1e-5, np.float64: 1e-12}
-TOL_INC = {np.float32: 1e-3, np.float64: 1e-10}
+TOL_INC = {np.float32: 1e-5, np.float64: 1e-10}
 
 
 def _tdt(dtype):
@@ -39,10 +41,23 @@ def _spec(n_s, n_x, L=22.0, seed=(120, 0), map_="rational", scale=40.0):
                               0.2, True, seed, map_, scale)
 
 
+def _storage_excess(got, ref, dtype):
+    """|got - ref| beyond the rounding of the exact value to the state dtype
+    (half an ulp of the larger of |got| and |ref|), for the real and the
+    imaginary parts."""
+    out = []
+    for g, r in ((np.real(got), np.real(ref)), (np.imag(got), np.imag(ref))):
+        g, r = np.asarray(g, np.float64), np.asarray(r, np.float64)
+        mag = np.maximum(np.abs(g), np.abs(r)).astype(dtype)
+        half_ulp = 0.5 * np.spacing(mag).astype(np.float64)
+        out.append(np.maximum(np.abs(g - r) - half_ulp, 0.0))
+    return np.maximum(out[0], out[1])
+
+
 def _check(got, ref, U, dtype):
     assert np.array_equal(got[0], U[0]) and np.array_equal(got[-1], U[-1])
     err = np.linalg.norm(got - ref) / np.linalg.norm(ref)
-    inc = np.abs(got - ref).max() / np.abs(ref - U).max()
+    inc = _storage_excess(got, ref, dtype).max() / np.abs(ref - U).max()
     assert err <= TOL[dtype], err
     assert inc <= TOL_INC[dtype], inc
     return err, inc

@@ -31,8 +31,11 @@ def test_noalloc_cost_matches_problem_entry_point(dtype):
     import paper_2301_11704_amd as ksc
     npdt = np.float32 if dtype == torch.float32 else np.float64
     tol = 1e-5 if dtype == torch.float32 else 1e-12
-    cases = [(64, 1024, 128, 66.0, "finite", 20.0), (5, 300, 64, 39.0, "rational", 40.0)]
-    for n_c, n_s, n_x, L, map_, scale in cases:  # the second call on a smaller batch
+    # each call on a smaller batch than the one before (the last two: 16 lanes
+    # per row in FP32 at N_x = 256, then one row per lane)
+    cases = [(64, 1024, 128, 66.0, "finite", 20.0), (2, 2048, 256, 100.0, "rational", 40.0),
+             (5, 300, 64, 39.0, "rational", 40.0)]
+    for n_c, n_s, n_x, L, map_, scale in cases:
         desc = ksc.CurveDesc(n_s, n_x, L, map_, scale)
         prob = ksc.Problem([desc] * n_c, dtype=dtype)
         X = prob.new_state()
