@@ -36,6 +36,8 @@ from .ks import (  # noqa: F401
     step_odd,
     implicit_s_operator,
     step_implicit_s,
+    solve_implicit_s,
+    precondition_implicit_s,
     step_implicit_s_odd,
     descend_implicit_s_momentum,
     from_physical_curve,

@@ -486,16 +486,42 @@ def step_implicit_s(c: Curve, U: np.ndarray, dtau: float) -> np.ndarray:
     of J^2.
     """
     U = _clean(c, U)
-    Ad = adjoint(c, U)
-    out = U.copy()
+    return U + solve_implicit_s(c, adjoint(c, U), dtau)
+
+
+def solve_implicit_s(c: Curve, Ad: np.ndarray, dtau: float) -> np.ndarray:
+    """The increment of ``step_implicit_s`` for the adjoint field Ad:
+    (I + dtau B_k) delta_k = -dtau Ad_k on the interior rows of every mode k;
+    zero on the end rows and for Im of mode 0."""
+    delta = np.zeros_like(Ad, dtype=np.complex128)
     ni = c.n_s - 2
     if ni <= 0:
-        return out
+        return delta
     for k in range(c.K + 1):
         M = np.eye(ni) + dtau * implicit_s_operator(c, k)
-        out[1:-1, k] = U[1:-1, k] + np.linalg.solve(M, -dtau * Ad[1:-1, k])
-    out[:, 0] = out[:, 0].real
-    return out
+        delta[1:-1, k] = np.linalg.solve(M, -dtau * Ad[1:-1, k])
+    delta[:, 0] = delta[:, 0].real
+    return delta
+
+
+def precondition_implicit_s(c: Curve, G: np.ndarray, dtau: float) -> np.ndarray:
+    """The implicit-in-s increment for a given Euclidean gradient G (the
+    layout of ``grad``): ``solve_implicit_s`` of L^dagger = G / (2 w_j L c_k)
+    on the interior rows.  As a map of the stored real and imaginary parts it
+    is -H0 G with H0 = dtau (I + dtau B)^{-1} (2 w L c)^{-1}: B is
+    self-adjoint and positive semi-definite in the w-weighted inner product,
+    so H0 is symmetric positive definite in the plain Euclidean one (the
+    initial inverse Hessian of a quasi-Newton method over the state, whose
+    gradient is G).
+
+    Parity: pinned by the symmetry and positivity of H0 in the Euclidean
+    inner product (tests/test_oracle_implicit_s.py) and, through
+    ``step_implicit_s``, by the Jacobian pin of ``implicit_s_operator``.
+    """
+    Ad = np.zeros_like(G, dtype=np.complex128)
+    if c.n_s > 2:
+        Ad[1:-1] = G[1:-1] / (2.0 * c.w[1:-1, None] * c.L * c.c[None, :])
+    return solve_implicit_s(c, Ad, dtau)
 
 
 def step_implicit_s_odd(c: Curve, B: np.ndarray, dtau: float) -> np.ndarray:

@@ -152,3 +152,47 @@ def test_momentum_descent_reduces_to_implicit_steps_and_accelerates():
     for _ in range(40):
         p40 = oracle.step_implicit_s(c, p40, 0.01)
     assert oracle.J2(c, m) < oracle.J2(c, p40)
+
+
+def test_precondition_is_symmetric_positive_definite_in_the_euclidean_product():
+    """The implicit-in-s preconditioner G -> -H0 G (``precondition_implicit_s``)
+    as a map of the stored real and imaginary parts: <a, H0 b> = <H0 a, b> and
+    <a, H0 a> > 0 for seeded gradient-shaped a, b (zero on the end rows and
+    for Im of mode 0), on both maps; on the rational map a constant weight
+    in place of w_j breaks the symmetry.  Applied to the gradient it is the
+    increment of the implicit-in-s step."""
+    import ksinputs
+    rng = np.random.default_rng(7)
+    for map_, scale in (("rational", 30.0), ("finite", 5.0)):
+        c = oracle.Curve(33, 16, 22.0, map_, scale)
+        K1 = c.K + 1
+
+        def vec():
+            v = rng.standard_normal((c.n_s, K1)) + 1j * rng.standard_normal((c.n_s, K1))
+            v[0] = v[-1] = 0
+            v[:, 0] = v[:, 0].real
+            return v
+
+        def dot(x, y):
+            return float(np.sum(x.real * y.real + x.imag * y.imag))
+
+        for dtau in (0.01, 1.0):
+            a, b = vec(), vec()
+            Ha = -oracle.precondition_implicit_s(c, a, dtau)
+            Hb = -oracle.precondition_implicit_s(c, b, dtau)
+            assert abs(dot(a, Hb) - dot(Ha, b)) <= 1e-12 * abs(dot(a, Hb)), (dot(a, Hb), dot(Ha, b))
+            assert dot(a, Ha) > 0 and dot(b, Hb) > 0
+            # the same map without the metric weight is not symmetric
+            w_saved = c.w.copy()
+            c.w = np.ones_like(c.w) * c.w.mean()
+            Hb_bad = -oracle.precondition_implicit_s(c, b, dtau)
+            Ha_bad = -oracle.precondition_implicit_s(c, a, dtau)
+            c.w = w_saved
+            if map_ == "rational":
+                assert abs(dot(a, Hb_bad) - dot(Ha_bad, b)) > 1e-6 * abs(dot(a, Hb_bad))
+        spec = ksinputs.CurveSpec(33, 16, 22.0, 4, 1.0, 4, 0.2, True, (131, 0), map_, scale)
+        _, _, U = ksinputs.make_curve(spec, K1)
+        U[:, 0] = U[:, 0].real
+        step = oracle.step_implicit_s(c, U, 0.1)
+        inc = oracle.precondition_implicit_s(c, oracle.grad(c, U), 0.1)
+        assert np.abs(U + inc - step).max() <= 1e-13 * np.abs(step).max()
