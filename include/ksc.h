@@ -253,6 +253,21 @@ ksc_status ksc_get_scheme(const ksc_problem* p, int32_t* scheme);
 ksc_status ksc_set_momentum(ksc_problem* p, double beta);
 ksc_status ksc_get_momentum(const ksc_problem* p, double* beta);
 
+/* The implicit-in-s increment for a given Euclidean gradient (an extension,
+ * not in the paper): on the interior rows of every mode k,
+ *     (I + dtau B_k) out_k = -dtau grad_k / (2 w_j L c_k),
+ * B_k = A_k^2 - D m D the linear part of the adjoint flow (the solve of the
+ * implicit-in-s step, which this is for grad = the gradient of the state);
+ * zero on the end rows and for Im of mode 0.  As a map of the stored real
+ * and imaginary parts, out = -H0 grad with H0 symmetric positive definite
+ * in the plain Euclidean inner product: the initial inverse Hessian of a
+ * quasi-Newton descent over the state (paper_2301_11704_amd/lbfgs.py).
+ * grad, out: device arrays in the state layout and dtype, distinct
+ * (KSC_ERR_ARG otherwise); dtau > 0.  Needs the implicit-in-s scheme set
+ * (ksc_set_scheme), else KSC_ERR_UNSUPPORTED.  Enqueued on the problem's
+ * stream; allocates nothing. */
+ksc_status ksc_precondition(ksc_problem* p, const void* grad, void* out, double dtau);
+
 /* Choose the launch shape (waves per tile, persistent or not) by timing the
  * candidates on scratch buffers; the choice is cached in the JSON file at
  * cache_path (nullable: no file) keyed by device, ROCm version and problem

@@ -29,7 +29,7 @@ EXPORTED = (
     "ksc_phys_to_spec", "ksc_spec_to_phys", "ksc_eval_J", "ksc_eval_grad", "ksc_step",
     "ksc_descend", "ksc_tune", "ksc_set_launch", "ksc_get_launch", "ksc_query_flags",
     "ksc_set_timing", "ksc_read_timing", "ksc_set_scheme", "ksc_get_scheme", "ksc_set_momentum",
-    "ksc_get_momentum", "ksc_eval_J_noalloc", "ksc_last_error",
+    "ksc_get_momentum", "ksc_precondition", "ksc_eval_J_noalloc", "ksc_last_error",
 )
 
 
@@ -98,6 +98,7 @@ def lib() -> ctypes.CDLL:
         "ksc_set_scheme": (i32, [vp, i32]),
         "ksc_get_scheme": (i32, [vp, ctypes.POINTER(i32)]),
         "ksc_set_momentum": (i32, [vp, dbl]),
+        "ksc_precondition": (i32, [vp, vp, vp, dbl]),
         "ksc_get_momentum": (i32, [vp, ctypes.POINTER(dbl)]),
         "ksc_query_flags": (i32, [vp, ctypes.POINTER(ctypes.c_uint32)]),
         "ksc_set_timing": (i32, [vp, i32]),

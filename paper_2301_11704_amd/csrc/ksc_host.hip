@@ -316,6 +316,7 @@ struct ksc_problem {
   int scheme = KSC_SCHEME_PAPER;
   double momentum = 0.0;  // heavy-ball momentum of the implicit-in-s descent (ksc_set_momentum)
   void* d_G = nullptr;
+  void* d_zero = nullptr;  // a zero state: the base of ksc_precondition's solve
   ksc::SimpBlock* d_simp = nullptr;
   int n_simp = 0;
   int simp_chunk = 16;
@@ -1030,15 +1031,19 @@ ksc_status build_simp(ksc_problem* p) {
   KSC_HIP(hipMemcpy(p->d_simp, b.data(), b.size() * sizeof(ksc::SimpBlock),
                     hipMemcpyHostToDevice));
   if (!p->d_G) KSC_HIP(hipMalloc(&p->d_G, p->state_bytes()));
+  if (!p->d_zero) {
+    KSC_HIP(hipMalloc(&p->d_zero, p->state_bytes()));
+    KSC_HIP(hipMemset(p->d_zero, 0, p->state_bytes()));
+  }
   return KSC_OK;
 }
 
 template <typename T>
-ksc_status launch_simp_t(ksc_problem* p, const void* in, void* out, double dtau, double beta,
-                         const uint8_t* active, hipStream_t s) {
+ksc_status launch_simp_t(ksc_problem* p, const void* in, const void* grad, void* out, double dtau,
+                         double beta, const uint8_t* active, hipStream_t s) {
   ksc::SimpArgs<T> a{};
   a.in = static_cast<const T*>(in);
-  a.grad = static_cast<const T*>(p->d_G);
+  a.grad = static_cast<const T*>(grad);
   a.out = static_cast<T*>(out);
   a.curves = p->d_cd;
   a.cs = static_cast<const T*>(p->d_cs);
@@ -1068,8 +1073,8 @@ ksc_status step_once(ksc_problem* p, const void* in, void* out, double dtau, dou
   ksc_status st = run(p, ksc::MODE_GRAD, in, p->d_G, nullptr, active, J2, nullptr, track,
                       finalize, s);
   if (st != KSC_OK) return st;
-  return p->dtype == KSC_F64 ? launch_simp_t<double>(p, in, out, dtau, beta, active, s)
-                             : launch_simp_t<float>(p, in, out, dtau, beta, active, s);
+  return p->dtype == KSC_F64 ? launch_simp_t<double>(p, in, p->d_G, out, dtau, beta, active, s)
+                             : launch_simp_t<float>(p, in, p->d_G, out, dtau, beta, active, s);
 }
 
 template <typename T>
@@ -1449,7 +1454,7 @@ ksc_status ksc_destroy(ksc_problem* p) {
   void* bufs[] = {p->d_bounds, p->d_cd,  p->d_tiles, p->d_cs,    p->d_wlT,    p->d_wlD,
                   p->d_A,   p->d_pre,   p->d_sqrtL, p->d_part,   p->d_prevJ2,
                   p->d_flags, p->d_rose, p->d_J2,  p->d_edge,  p->d_dpool,  p->d_spec,  p->d_Y,
-                  p->d_WR,  p->d_P,   p->d_sgroups, p->d_kpart, p->d_G, p->d_simp};
+                  p->d_WR,  p->d_P,   p->d_sgroups, p->d_kpart, p->d_G, p->d_zero, p->d_simp};
   for (void* b : bufs)
     if (b) hipFree(b);
   delete p;
@@ -1663,6 +1668,20 @@ ksc_status ksc_get_momentum(const ksc_problem* p, double* beta) {
   if (!p || !beta) return fail(KSC_ERR_ARG, "ksc_get_momentum: null pointer");
   *beta = p->momentum;
   return KSC_OK;
+}
+
+ksc_status ksc_precondition(ksc_problem* p, const void* grad, void* out, double dtau) {
+  if (!p || !grad || !out) return fail(KSC_ERR_ARG, "ksc_precondition: null pointer");
+  if (grad == out) return fail(KSC_ERR_ARG, "ksc_precondition: grad and out must differ");
+  if (!(dtau > 0) || !std::isfinite(dtau))
+    return fail(KSC_ERR_ARG, "ksc_precondition: dtau must be > 0");
+  if (p->scheme != KSC_SCHEME_IMPLICIT_S || !p->d_simp || !p->d_zero)
+    return fail(KSC_ERR_UNSUPPORTED,
+                "ksc_precondition: needs ksc_set_scheme(KSC_SCHEME_IMPLICIT_S) first");
+  // the implicit-in-s solve of the step, on a zero state: out = 0 + delta(grad)
+  return p->dtype == KSC_F64
+             ? launch_simp_t<double>(p, p->d_zero, grad, out, dtau, 0.0, nullptr, p->stream)
+             : launch_simp_t<float>(p, p->d_zero, grad, out, dtau, 0.0, nullptr, p->stream);
 }
 
 ksc_status ksc_get_scheme(const ksc_problem* p, int32_t* scheme) {

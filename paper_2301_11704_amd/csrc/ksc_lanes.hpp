@@ -194,6 +194,10 @@ __device__ __forceinline__ void r2c_lanes_split(const T (&in)[N / L], int p, cpl
   row_sync();
 }
 
+// The fused tile evaluation (as tile_body in ksc_tile.hpp: staging, pass 0 in
+// FP64, the residual and its partial sums, the residual exchange, pass 1, the
+// adjoint, the output) with the R = 64W/L rows of the tile spread over L
+// lanes each.
 template <int NX, typename T, int W, int MODE, int L>
 __device__ __forceinline__ void tile_body_lanes(const KernelArgs<T>& a, const CurveDev& cd, int c,
                                                 int j0, int tile, cplx<T>* buf) {

@@ -50,6 +50,8 @@ class GpuBackend:
         self._torch = torch
         self.scratch = torch.empty_like(state)
         self.active = torch.ones(problem.n_curves, dtype=torch.uint8, device=state.device)
+        self._lbfgs = None
+        self._lbfgs_key = None
 
     @property
     def dtype(self) -> str:
@@ -61,6 +63,23 @@ class GpuBackend:
     def run(self, n_steps: int, dtau: float, every: int) -> np.ndarray:
         tr = self.prob.descend(self.state, n_steps, dtau, every=every, scratch=self.scratch,
                                active=self.active)
+        return tr.cpu().numpy()
+
+    def run_lbfgs(self, n_iter: int, dtau: float, every: int, m: int) -> np.ndarray:
+        """n_iter batched L-BFGS iterations (lbfgs.py) on the active curves
+        from the current state, H0 = the implicit-in-s solve at dtau; the
+        memory carries over between calls while the state is the one the
+        last call left.  Returns the J2 of every `every`-th iteration."""
+        from .lbfgs import BatchLBFGS, TorchOps
+        torch = self._torch
+        key = (float(dtau), int(m))
+        if self._lbfgs is None or self._lbfgs_key != key or \
+                not torch.equal(self._lbfgs.x, self.state):
+            self._lbfgs = BatchLBFGS(TorchOps(self.prob, dtau), m=m)
+            self._lbfgs.start(self.state)
+            self._lbfgs_key = key
+        tr = self._lbfgs.run(n_iter, self.active.bool(), every)
+        self.state.copy_(self._lbfgs.x)
         return tr.cpu().numpy()
 
     def J2(self) -> np.ndarray:
@@ -117,7 +136,7 @@ def descend_to(backend, dtau: float, J_target: float = 1e-8, max_steps: int = 10
                stall_records: int = 10, fp64_finish: bool = True, Jarc_target: float | None = None,
                min_dtau: float = 1e-9, rise_tol: float = 1e-3, checkpoint: str | None = None,
                checkpoint_every: int | None = None, resume: bool = False, log: DescentLog | None = None,
-               progress=None, momentum: float = 0.0):
+               progress=None, momentum: float = 0.0, lbfgs: int = 0, lbfgs_chunk: int = 500):
     """Run the descent; returns (backend, DescentLog).  The returned backend may
     be a promoted (FP64) one holding the final state.  progress(log, J) is
     called after every accepted chunk with the per-curve J.  momentum > 0
@@ -125,7 +144,10 @@ def descend_to(backend, dtau: float, J_target: float = 1e-8, max_steps: int = 10
     the second FP64 chunk on, for the slow final approach; the FP32 phase, far
     from the minimum, runs the plain steps.  A chunk whose cost rose with the
     momentum on is redone with plain steps at the same dtau, and the momentum
-    resumes after it; a rise without momentum halves dtau."""
+    resumes after it; a rise without momentum halves dtau.  lbfgs = m > 0
+    (implicit-in-s scheme) runs that late phase as batched L-BFGS iterations
+    instead (memory m, lbfgs_chunk iterations per chunk, H0 the implicit-in-s
+    solve at dtau; an iteration counts as a step and tau does not advance)."""
     every = max(1, int(every))
     chunk = int(chunk or every)
     chunk = max(every, (chunk // every) * every)
@@ -149,9 +171,14 @@ def descend_to(backend, dtau: float, J_target: float = 1e-8, max_steps: int = 10
     momentum_on = False
     switched_at = log.steps if log.dtype == "f64" else 1 << 62
     while log.steps < max_steps:
-        n = min(chunk, max_steps - log.steps)
-        n = max(every, (n // every) * every)
-        tr = backend.run(n, dtau, every)
+        late = backend.dtype == "f64" and log.steps > switched_at
+        if lbfgs > 0 and late:
+            n = max(1, min(int(lbfgs_chunk), max_steps - log.steps))
+            tr = backend.run_lbfgs(n, dtau, n, lbfgs)
+        else:
+            n = min(chunk, max_steps - log.steps)
+            n = max(every, (n // every) * every)
+            tr = backend.run(n, dtau, every)
         J2 = backend.J2()
         Jn = np.sqrt(np.abs(J2))
         # a rise beyond rounding noise (rise_tol, relative) or a non-finite cost;
@@ -175,8 +202,10 @@ def descend_to(backend, dtau: float, J_target: float = 1e-8, max_steps: int = 10
                 log.events.append((log.steps, "dtau below minimum; stopping"))
                 break
             continue
+        lbfgs_chunk_done = lbfgs > 0 and late
         log.steps += n
-        log.tau += n * dtau
+        if not lbfgs_chunk_done:
+            log.tau += n * dtau
         log.dtau = dtau
         log.J_history.append((log.steps, Jn.copy()))
         Ja = None
@@ -185,7 +214,7 @@ def descend_to(backend, dtau: float, J_target: float = 1e-8, max_steps: int = 10
             log.Jarc_history.append((log.steps, Ja.copy()))
         if progress is not None:
             progress(log, Jn)
-        if momentum > 0 and not momentum_on and backend.dtype == "f64" and \
+        if momentum > 0 and lbfgs <= 0 and not momentum_on and backend.dtype == "f64" and \
                 log.steps > switched_at:
             # momentum from the second FP64 chunk on: the first plain FP64
             # chunk removes the FP32 rounding noise, whose fast initial decrease
@@ -272,6 +301,11 @@ def main(argv=None):
     ap.add_argument("--scheme", default="paper", choices=["paper", "implicit_s"],
                     help="descent step: the paper's (A_k^2 implicit) or implicit_s (the whole "
                          "linear part, d/ds included, implicit: larger stable dtau)")
+    ap.add_argument("--lbfgs", type=int, default=0, metavar="M",
+                    help="batched L-BFGS with memory M (H0 the implicit-in-s solve) from the "
+                         "second FP64 chunk on instead of further steps (0: off)")
+    ap.add_argument("--lbfgs-chunk", type=int, default=500,
+                    help="L-BFGS iterations between the driver's decisions")
     ap.add_argument("--momentum", type=float, default=0.0,
                     help="heavy-ball momentum beta of the implicit_s descent from the FP64 switch "
                          "on (0: off; include/ksc.h ksc_set_momentum)")
@@ -314,6 +348,8 @@ def main(argv=None):
         if any(np.abs(U.real).max() > 0 for U in Us):
             raise ValueError("the odd subspace needs inversion-symmetric curves (u_hat_k = i b_k)")
         Us = [np.ascontiguousarray(U[:, 1:].imag) for U in Us]
+    if args.lbfgs > 0 and args.scheme != "implicit_s":
+        raise ValueError("--lbfgs takes its initial inverse Hessian from --scheme implicit_s")
     prob.set_scheme(args.scheme)
     prob.tune(None)
     X = prob.new_state()
@@ -341,7 +377,8 @@ def main(argv=None):
                          every=args.every, chunk=args.chunk, switch_J=args.switch,
                          stall_records=args.stall_records, checkpoint=args.checkpoint,
                          checkpoint_every=args.checkpoint_every, resume=args.resume,
-                         progress=report, Jarc_target=args.jarc_target, momentum=args.momentum)
+                         progress=report, Jarc_target=args.jarc_target, momentum=args.momentum,
+                         lbfgs=args.lbfgs, lbfgs_chunk=args.lbfgs_chunk)
     J = np.sqrt(np.abs(b2.J2()))
     ok = J < args.target
     if args.jarc_target is not None:

@@ -259,6 +259,18 @@ class Problem:
         scheme (include/ksc.h, ksc_set_momentum); 0 turns it off."""
         check(lib().ksc_set_momentum(self._h, float(beta)))
 
+    def precondition(self, grad: torch.Tensor, out: torch.Tensor | None = None,
+                     dtau: float = 0.05) -> torch.Tensor:
+        """The implicit-in-s increment for the Euclidean gradient `grad`
+        (include/ksc.h, ksc_precondition): -H0 grad with H0 symmetric positive
+        definite; needs set_scheme("implicit_s")."""
+        self._check_state(grad, "grad")
+        out = torch.empty_like(grad) if out is None else out
+        self._check_state(out, "out")
+        self._sync_stream()
+        check(lib().ksc_precondition(self._h, _ptr(grad), _ptr(out), float(dtau)))
+        return out
+
     @property
     def momentum(self) -> float:
         v = ctypes.c_double()

@@ -6,6 +6,7 @@ already disagree in the unweighted norm at the large-A_k modes."""
 from __future__ import annotations
 
 import numpy as np
+import torch
 
 import ksinputs
 import oracle
@@ -77,3 +78,54 @@ def oracle_descent(c: oracle.Curve, U: np.ndarray, n: int, dtau: float, storage=
         if storage is not None:
             X = ksinputs.round_to(X, storage)
     return (X, tr) if trace_every else X
+
+
+class OracleOps:
+    """The model of paper_2301_11704_amd.lbfgs.BatchLBFGS from the FP64 oracle
+    (gradient, cost, implicit-in-s preconditioner) over flat FP64 torch CPU
+    vectors in the library's state layout (curve after curve,
+    row-major, re/im interleaved)."""
+
+    def __init__(self, curves, dtau):
+        self.curves = curves
+        self.dtau = dtau
+        self.shapes = [(c.n_s, c.K + 1) for c in curves]
+        self.sizes = [2 * n * k for n, k in self.shapes]
+        self.offsets = np.concatenate([[0], np.cumsum(self.sizes)[:-1]]).astype(int)
+        self.nc = len(curves)
+
+    def unflat(self, x, i):
+        o, n = self.offsets[i], self.sizes[i]
+        v = x[o:o + n].numpy().reshape(*self.shapes[i], 2)
+        return v[..., 0] + 1j * v[..., 1]
+
+    def flat(self, arrs):
+        return torch.from_numpy(np.concatenate(
+            [np.stack([a.real, a.imag], axis=-1).ravel() for a in arrs]))
+
+    def grad(self, x):
+        Us = [self.unflat(x, i) for i in range(self.nc)]
+        G = self.flat([oracle.grad(c, U) for c, U in zip(self.curves, Us)])
+        return G, torch.tensor([oracle.J2(c, U) for c, U in zip(self.curves, Us)],
+                               dtype=torch.float64)
+
+    def J2(self, x):
+        return torch.tensor([oracle.J2(c, self.unflat(x, i)) for i, c in enumerate(self.curves)],
+                            dtype=torch.float64)
+
+    def precond(self, g):
+        return -self.flat([oracle.precondition_implicit_s(c, self.unflat(g, i), self.dtau)
+                           for i, c in enumerate(self.curves)])
+
+    def dot(self, a, b):
+        return torch.tensor([float(torch.dot(a[o:o + n], b[o:o + n]))
+                             for o, n in zip(self.offsets, self.sizes)], dtype=torch.float64)
+
+    def scale(self, v, a):
+        out = torch.empty_like(v)
+        for i, (o, n) in enumerate(zip(self.offsets, self.sizes)):
+            out[o:o + n] = v[o:o + n] * float(a[i])
+        return out
+
+    def axpy(self, v, a, x):
+        return v + self.scale(x, a)

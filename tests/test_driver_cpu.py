@@ -191,3 +191,29 @@ def test_rise_with_momentum_redoes_the_chunk_without_it():
     # a plain chunk, the overshooting momentum chunk, its plain redo, then
     # momentum to the end
     assert b.betas[:4] == [0.0, 0.9, 0.0, 0.9] and set(b.betas[3:]) == {0.9}
+
+
+class _LbfgsBackend(_MomentumBackend):
+    """Scripted: steps reduce J by 10% per chunk; L-BFGS chunks halve it."""
+
+    def __init__(self):
+        super().__init__()
+        self.lbfgs_calls = []
+
+    def run_lbfgs(self, n_iter, dtau, every, m):
+        self.lbfgs_calls.append((n_iter, dtau, m))
+        self.J = self.J * 0.5
+        return np.tile(self.J ** 2, (max(1, n_iter // every), 1))
+
+
+def test_lbfgs_runs_the_late_fp64_phase():
+    """With lbfgs = m the driver runs the chunks after the first FP64 chunk as
+    L-BFGS chunks (lbfgs_chunk iterations each, counted as steps, tau frozen)
+    and never turns the momentum on."""
+    b = _LbfgsBackend()
+    _, log = descend_to(b, dtau=0.05, J_target=1e-3, max_steps=10_000, every=10, chunk=10,
+                        momentum=0.9, lbfgs=5, lbfgs_chunk=7)
+    assert b.lbfgs_calls and all(c == (7, 0.05, 5) for c in b.lbfgs_calls)
+    assert set(b.betas) == {0.0} and len(b.betas) == 1
+    assert log.converged.all()
+    assert log.tau == 10 * 0.05 and log.steps == 10 + 7 * len(b.lbfgs_calls)
