@@ -101,3 +101,30 @@ def test_lbfgs_iterates_match_the_oracle_model():
             assert err <= 1e-9, (it, c, err)
     print("L-BFGS J2 after 6 iterations:", prev.numpy(), "from",
           [oracle.J2(c, U) for c, U in zip(curves, Us)], flush=True)
+
+
+def test_workload4_reduced_descent_reaches_1e8_with_lbfgs():
+    """Two curves of workload 4 on 256 rows: implicit-in-s steps in FP32, the
+    FP64 switch at J = 2e-3, then batched L-BFGS (memory 8) to J < 1e-8; the
+    final J agrees with the oracle's J of the downloaded state."""
+    import paper_2301_11704_amd as ksc
+    from paper_2301_11704_amd.driver import GpuBackend, descend_to
+    specs, Us = ksinputs.config4_curves(4, 256)
+    pick = [0, 3]
+    specs, Us = [specs[i] for i in pick], [Us[i] for i in pick]
+    prob = ksc.Problem([ksc.CurveDesc(s.n_s, s.n_x, s.L, s.map, s.scale, s.s0) for s in specs],
+                       dtype=torch.float32)
+    prob.set_scheme("implicit_s")
+    X = prob.new_state()
+    for c, U in enumerate(Us):
+        prob.upload(X, c, ksinputs.round_to(U, np.float32))
+    b, log = descend_to(GpuBackend(prob, X), dtau=0.05, J_target=1e-8, max_steps=400_000,
+                        every=1000, chunk=20000, switch_J=2e-3, stall_records=5, lbfgs=8,
+                        lbfgs_chunk=500)
+    print("events:", log.events, "steps:", log.steps, flush=True)
+    assert b.dtype == "f64" and log.converged.all()
+    J = np.sqrt(b.J2())
+    for c, s in enumerate(specs):
+        U = b.prob.download(b.state, c)
+        ref = np.sqrt(oracle.J2(oracle_curve(s), U))
+        assert J[c] < 1e-8 and abs(J[c] - ref) <= 1e-5 * ref, (J[c], ref)
