@@ -159,10 +159,11 @@ class BatchLBFGS:
             Jt = ops.J2(ops.axpy(self.x, step, d))
             ok = ~act | (Jt <= J2 + self.c1 * step * gd)
             flags[1] = ok.all().cpu()
-        failed = ~ok
-        # no acceptable step along d: stay, and forget the memory
-        step = torch.where(failed, torch.zeros_like(step), step)
-        self._forget(failed)
+        if not bool(flags[1]):
+            # no acceptable step along d: stay, and forget the memory
+            failed = ~ok
+            step = torch.where(failed, torch.zeros_like(step), step)
+            self._forget(failed)
         x_new = ops.axpy(self.x, step, d)
         g_new, J2_new = ops.grad(x_new)
         s = x_new - self.x
@@ -174,10 +175,18 @@ class BatchLBFGS:
         keep = (step > 0) & (sy > 1e-12 * torch.sqrt(ops.dot(s, s) * yy))
         rho = torch.where(keep, 1.0 / torch.where(keep, sy, torch.ones_like(sy)),
                           torch.zeros_like(sy))
-        yHy = ops.dot(y, ops.precond(y))
+        Hy = ops.precond(y)
+        yHy = ops.dot(y, Hy)
         ok_g = keep & (yHy > 0)
         self.gamma = torch.where(ok_g, sy / torch.where(ok_g, yHy, torch.ones_like(yHy)),
                                  self.gamma)
+        self._push(s, y, Hy, keep, rho)
+        self.x, self.g = x_new, g_new.clone()
+        self.J2 = torch.where(act, J2_new, J2)
+        return self.J2
+
+    def _push(self, s, y, Hy, keep, rho):
+        """Store the pair (s, y) (inert where keep is False)."""
         self.S.append(s)
         self.Y.append(y)
         self.rho.append(rho)
@@ -185,9 +194,6 @@ class BatchLBFGS:
             self.S.pop(0)
             self.Y.pop(0)
             self.rho.pop(0)
-        self.x, self.g = x_new, g_new.clone()
-        self.J2 = torch.where(act, J2_new, J2)
-        return self.J2
 
     def run(self, n: int, active, every: int = 1):
         """n iterations; the J2 of every `every`-th iteration, [n // every, n_curves]."""
@@ -199,4 +205,3 @@ class BatchLBFGS:
         if rows:
             return torch.stack(rows)
         return torch.zeros((0, self.ops.nc), dtype=torch.float64, device=self.x.device)
-
