@@ -370,3 +370,23 @@ def test_workload4_reduced_descent_reaches_1e8_through_fp64():
         U = b.prob.download(b.state, c)
         ref = np.sqrt(oracle.J2(oracle_curve(s), U))
         assert J[c] < 1e-8 and abs(J[c] - ref) <= 1e-5 * ref, (J[c], ref)
+
+
+def test_set_scheme_again_keeps_the_descent_graph_valid():
+    """Selecting the implicit-in-s scheme a second time keeps the solve table
+    (and the captured descent graph that points at it) valid: 20 graph steps,
+    set_scheme again, 20 more graph steps equal 40 eager steps."""
+    spec = _spec(70, 32, 22.0, (126, 0), "finite", 5.0)
+    prob = _problem([spec], np.float64)
+    X = prob.new_state()
+    prob.upload(X, 0, seeded_state(spec, np.float64))
+    Y = X.clone()
+    prob.descend(X, 20, 0.05, every=10, trace=False)
+    prob.set_scheme("implicit_s")
+    prob.descend(X, 20, 0.05, every=10, trace=False)
+    Z = torch.empty_like(Y)
+    for _ in range(20):
+        prob.step(Y, Z, 0.05)
+        prob.step(Z, Y, 0.05)
+    torch.cuda.synchronize()
+    assert torch.equal(X, Y)
