@@ -180,13 +180,14 @@ class BatchLBFGS:
         ok_g = keep & (yHy > 0)
         self.gamma = torch.where(ok_g, sy / torch.where(ok_g, yHy, torch.ones_like(yHy)),
                                  self.gamma)
-        self._push(s, y, Hy, keep, rho)
+        self._push(s, y, rho)
         self.x, self.g = x_new, g_new.clone()
         self.J2 = torch.where(act, J2_new, J2)
         return self.J2
 
-    def _push(self, s, y, Hy, keep, rho):
-        """Store the pair (s, y) (inert where keep is False)."""
+    def _push(self, s, y, rho):
+        """Store the pair (s, y) with weight rho (a curve whose rho is 0
+        ignores the pair: both loops of the recursion skip it)."""
         self.S.append(s)
         self.Y.append(y)
         self.rho.append(rho)

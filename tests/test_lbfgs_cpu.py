@@ -55,3 +55,131 @@ def test_monotone_and_faster_than_the_implicit_in_s_steps():
         for _ in range(40):
             U = oracle.step_implicit_s(curves[i], U, 0.05)
         assert float(J2[i]) < oracle.J2(curves[i], U), (float(J2[i]), oracle.J2(curves[i], U))
+
+
+class _DenseOps:
+    """A batch of small dense models for BatchLBFGS: curve i minimizes the
+    quadratic 1/2 x.A_i x - b_i.x with the initial inverse Hessian H0_i,
+    all symmetric positive definite."""
+
+    def __init__(self, A, b, H0):
+        self.A, self.b, self.H0 = A, b, H0
+        self.nc, self.n = b.shape
+
+    def _v(self, x):
+        return x.view(self.nc, self.n)
+
+    def grad(self, x):
+        X = self._v(x)
+        G = torch.einsum("cij,cj->ci", self.A, X) - self.b
+        return G.reshape(-1), self.J2(x)
+
+    def J2(self, x):
+        X = self._v(x)
+        AX = torch.einsum("cij,cj->ci", self.A, X)
+        return 0.5 * (X * AX).sum(1) - (self.b * X).sum(1)
+
+    def precond(self, g):
+        return torch.einsum("cij,cj->ci", self.H0, self._v(g)).reshape(-1)
+
+    def dot(self, a, b):
+        return (self._v(a) * self._v(b)).sum(1)
+
+    def scale(self, v, a):
+        return (self._v(v) * a[:, None]).reshape(-1)
+
+    def axpy(self, v, a, x):
+        return v + self.scale(x, a)
+
+
+def _spd(rng, nc, n, shift):
+    M = rng.standard_normal((nc, n, n))
+    return torch.from_numpy(M @ M.transpose(0, 2, 1) / n + shift * np.eye(n))
+
+
+def test_two_loop_recursion_is_the_dense_bfgs_update():
+    """The direction is -H g, H the inverse-BFGS update (Nocedal & Wright
+    eq. 6.17) applied to gamma H0 by the stored pairs, oldest first; only
+    the last m pairs count, and a pair of weight 0 is skipped."""
+    rng = np.random.default_rng(71)
+    nc, n, m = 3, 7, 4
+    H0 = _spd(rng, nc, n, 0.5)
+    ops = _DenseOps(_spd(rng, nc, n, 1.0), torch.zeros(nc, n, dtype=torch.float64), H0)
+    opt = BatchLBFGS(ops, m=m)
+    opt.start(torch.zeros(nc * n, dtype=torch.float64))
+    B = _spd(rng, nc, n, 1.0)
+    pairs = []
+    for k in range(6):
+        S = torch.from_numpy(rng.standard_normal((nc, n)))
+        Y = torch.einsum("cij,cj->ci", B, S)
+        rho = 1.0 / (S * Y).sum(1)
+        if k == 4:
+            rho[1] = 0.0
+        opt._push(S.reshape(-1), Y.reshape(-1), rho)
+        pairs.append((S, Y, rho))
+    assert len(opt.S) == m
+    opt.gamma = torch.tensor([0.7, 1.3, 2.1], dtype=torch.float64)
+    g = torch.from_numpy(rng.standard_normal(nc * n))
+    opt.g = g
+    d = opt.direction().view(nc, n)
+    eye = torch.eye(n, dtype=torch.float64)
+    for c in range(nc):
+        H = opt.gamma[c] * H0[c]
+        for S, Y, rho in pairs[-m:]:
+            V = eye - rho[c] * torch.outer(Y[c], S[c])
+            H = V.T @ H @ V + rho[c] * torch.outer(S[c], S[c])
+        ref = -(H @ g.view(nc, n)[c])
+        assert torch.allclose(d[c], ref, rtol=0, atol=1e-12 * ref.abs().max())
+
+
+def test_two_loop_recursion_meets_the_secant_condition():
+    """H y = s for the newest pair (the defining property of the update)."""
+    rng = np.random.default_rng(72)
+    nc, n = 2, 9
+    ops = _DenseOps(_spd(rng, nc, n, 1.0), torch.zeros(nc, n, dtype=torch.float64),
+                    _spd(rng, nc, n, 0.3))
+    opt = BatchLBFGS(ops, m=3)
+    opt.start(torch.zeros(nc * n, dtype=torch.float64))
+    B = _spd(rng, nc, n, 1.0)
+    for _ in range(3):
+        S = torch.from_numpy(rng.standard_normal((nc, n)))
+        Y = torch.einsum("cij,cj->ci", B, S)
+        opt._push(S.reshape(-1), Y.reshape(-1), 1.0 / (S * Y).sum(1))
+    opt.g = opt.Y[-1]
+    d = opt.direction()
+    assert torch.allclose(-d, opt.S[-1], rtol=0, atol=1e-12 * opt.S[-1].abs().max())
+
+
+def test_quadratic_minimum_is_the_linear_solve():
+    """On strictly convex quadratics the iterates reach A^-1 b (a library
+    solve) per curve, J^2 never rises, and the H0 scaling after an update
+    is s.y / y.H0 y.  The line search compares costs, so it resolves the
+    minimizer only to where 1/2 lambda_min |x - x*|^2 reaches the rounding
+    of the cost: |x - x*| ~ sqrt(2 eps |J*| / lambda_min)."""
+    rng = np.random.default_rng(73)
+    nc, n = 3, 12
+    A = _spd(rng, nc, n, 0.2)
+    b = torch.from_numpy(rng.standard_normal((nc, n)))
+    H0 = _spd(rng, nc, n, 1.0)
+    ops = _DenseOps(A, b, H0)
+    opt = BatchLBFGS(ops, m=n)
+    opt.start(torch.zeros(nc * n, dtype=torch.float64))
+    active = torch.ones(nc, dtype=torch.bool)
+    x0, g0 = opt.x.clone(), opt.g.clone()
+    prev = opt.J2.clone()
+    opt.iterate(active)
+    s = (opt.x - x0).view(nc, n)
+    y = (opt.g - g0).view(nc, n)
+    gam = (s * y).sum(1) / (y * torch.einsum("cij,cj->ci", H0, y)).sum(1)
+    assert torch.allclose(opt.gamma, gam, rtol=1e-13, atol=0)
+    for _ in range(200):
+        J2 = opt.iterate(active)
+        assert torch.all(J2 <= prev + 1e-12 * prev.abs())
+        prev = J2.clone()
+    ref = torch.linalg.solve(A, b)
+    Jmin = -0.5 * (b * ref).sum(1)
+    lam = torch.linalg.eigvalsh(A)[:, 0]
+    tol = 10 * torch.sqrt(2 * torch.finfo(torch.float64).eps * Jmin.abs() / lam)
+    err = torch.linalg.vector_norm(opt.x.view(nc, n) - ref, dim=1)
+    assert torch.all(err <= tol), (err, tol)
+    assert torch.all(tol <= 1e-6 * torch.linalg.vector_norm(ref, dim=1))
