@@ -23,20 +23,25 @@ import ksinputs  # noqa: E402
 import oracle  # noqa: E402
 
 
-def main(n_curves=64, n_samples=128, substeps=16, spinup_h=0.01):
-    L, n_x, T = 66.0, 128, 20.0
-    c = oracle.Curve(3, n_x, L)
-    K1 = c.K + 1
-    traj = np.zeros((n_curves, n_samples + 1, K1), dtype=np.complex64)
+L, N_X, T = 66.0, 128, 20.0
+
+
+def trajectory(i, n_samples=128, substeps=16, spinup_h=0.01):
+    """The FP64 trajectory piece of curve i, [n_samples + 1, K + 1]."""
+    c = oracle.Curve(3, N_X, L)
+    rng = np.random.default_rng(np.random.SeedSequence([4, i]))
+    u0 = ksinputs.smooth_coeffs(rng, 6, 1.0, c.K + 1)
+    a = oracle.etdrk4_integrate(c, u0, spinup_h, int(round(T / spinup_h)),
+                                sample_every=int(round(T / spinup_h)))[-1]
     h = T / n_samples / substeps
-    for i in range(n_curves):
-        rng = np.random.default_rng(np.random.SeedSequence([4, i]))
-        u0 = ksinputs.smooth_coeffs(rng, 6, 1.0, K1)
-        a = oracle.etdrk4_integrate(c, u0, spinup_h, int(round(T / spinup_h)),
-                                    sample_every=int(round(T / spinup_h)))[-1]
-        traj[i] = oracle.etdrk4_integrate(c, a, h, n_samples * substeps, sample_every=substeps)
-    np.savez_compressed(os.path.join(HERE, "c4_trajectories.npz"), traj=traj, L=L, n_x=n_x, T=T,
-                        h=h)
+    return oracle.etdrk4_integrate(c, a, h, n_samples * substeps, sample_every=substeps)
+
+
+def main(n_curves=64, n_samples=128, substeps=16):
+    traj = np.stack([trajectory(i, n_samples, substeps).astype(np.complex64)
+                     for i in range(n_curves)])
+    np.savez_compressed(os.path.join(HERE, "c4_trajectories.npz"), traj=traj, L=L, n_x=N_X, T=T,
+                        h=T / n_samples / substeps)
 
 
 if __name__ == "__main__":
