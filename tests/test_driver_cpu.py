@@ -2,6 +2,7 @@
 converged curves, promote to FP64, checkpoint and resume) exercised on the CPU
 with a backend built on the FP64 oracle.  No GPU."""
 import numpy as np
+import pytest
 
 import ksinputs
 import oracle
@@ -83,6 +84,7 @@ def _specs(n=2):
     return specs, Us
 
 
+@pytest.mark.filterwarnings("ignore::RuntimeWarning")  # the chunk overflows on purpose
 def test_rollback_and_halving_on_divergence():
     specs, Us = _specs(1)
     b = OracleBackend(specs, Us, "f64")

@@ -642,7 +642,8 @@ def test_J_arc_spectral_ds_converges_to_the_integral_in_s():
     L, S = 22.0, 8.0
 
     def curve_of_s(s):
-        sech, th = 1.0 / np.cosh(s / 4.0), np.tanh(s / 4.0)
+        e = np.exp(-np.abs(s) / 4.0)
+        sech, th = 2.0 * e / (1.0 + e * e), np.tanh(s / 4.0)  # no overflow as |s| grows
         # u = 0.6 sech cos(q1 x) + 0.4 sech tanh sin(q2 x): the coefficients
         # u_hat_1 = 0.3 sech, u_hat_2 = -0.2 i sech tanh of _decaying_curve
         A, dA = 0.6 * sech, -0.6 * th * sech / 4.0
