@@ -2,6 +2,7 @@
 model built from the FP64 oracle (gradient, cost and the implicit-in-s
 preconditioner of ``oracle.precondition_implicit_s``).  No GPU."""
 import numpy as np
+import pytest
 import torch
 
 import ksinputs
@@ -183,3 +184,90 @@ def test_quadratic_minimum_is_the_linear_solve():
     err = torch.linalg.vector_norm(opt.x.view(nc, n) - ref, dim=1)
     assert torch.all(err <= tol), (err, tol)
     assert torch.all(tol <= 1e-6 * torch.linalg.vector_norm(ref, dim=1))
+
+
+class _OracleProblem:
+    """The part of paper_2301_11704_amd.Problem that TorchOps uses, over
+    the FP64 oracle on the CPU: state layout curve after curve (re/im
+    interleaved rows), optionally with unused gaps between the curves whose
+    contents the model never reads (the preconditioner leaves NaN there,
+    the worst an uninitialized output buffer can hold)."""
+
+    def __init__(self, curves, gap=0):
+        self.curves = curves
+        self.n_curves = len(curves)
+        self.device = torch.device("cpu")
+        self.dtype = torch.float64
+        sizes = [2 * c.n_s * (c.K + 1) for c in curves]
+        self.offsets = [int(sum(sizes[:i])) + gap * i for i in range(len(curves))]
+        self.numel = self.offsets[-1] + sizes[-1] + gap
+
+    def new_state(self):
+        return torch.zeros(self.numel, dtype=self.dtype)
+
+    def view(self, state, c):
+        cur = self.curves[c]
+        n = 2 * cur.n_s * (cur.K + 1)
+        return state[self.offsets[c]:self.offsets[c] + n].view(cur.n_s, cur.K + 1, 2)
+
+    def _get(self, state, c):
+        v = self.view(state, c).numpy()
+        return v[..., 0] + 1j * v[..., 1]
+
+    def _put(self, state, c, U):
+        v = self.view(state, c)
+        v[..., 0] = torch.from_numpy(U.real)
+        v[..., 1] = torch.from_numpy(U.imag)
+
+    def eval_J(self, x):
+        return torch.tensor([oracle.J2(c, self._get(x, i)) for i, c in enumerate(self.curves)],
+                            dtype=torch.float64)
+
+    def eval_grad(self, x):
+        G = torch.zeros_like(x)
+        for i, c in enumerate(self.curves):
+            self._put(G, i, oracle.grad(c, self._get(x, i)))
+        return G, self.eval_J(x)
+
+    def precondition(self, g, out, dtau):
+        out.fill_(float("nan"))
+        for i, c in enumerate(self.curves):
+            self._put(out, i, oracle.precondition_implicit_s(c, self._get(g, i), dtau))
+        return out
+
+
+def _torch_ops_run(prob, Us, n_iter, m=4):
+    from paper_2301_11704_amd.lbfgs import TorchOps
+    x = prob.new_state()
+    for i, U in enumerate(Us):
+        prob._put(x, i, U)
+    opt = BatchLBFGS(TorchOps(prob, 0.05), m=m)
+    opt.start(x)
+    for _ in range(n_iter):
+        opt.iterate(torch.ones(prob.n_curves, dtype=torch.bool))
+    return opt, prob
+
+
+@pytest.mark.parametrize("uneven,gap", [(False, 0), (True, 0), (True, 6)])
+def test_torch_ops_follow_the_per_curve_model(uneven, gap):
+    """The tensor operations over the state layout (one reshape for curves of
+    equal size, a per-scalar curve index otherwise, gaps ignored) give the
+    iterates of the per-curve loops of the oracle model."""
+    specs = [ksinputs.CurveSpec(33 + (8 * i if uneven else 0), 16, 22.0, 4, 1.0, 4, 0.3, True,
+                                (160, i), "finite", 5.0) for i in range(3)]
+    curves = [oracle.Curve(s.n_s, s.n_x, s.L, s.map, s.scale) for s in specs]
+    Us = []
+    for s, c in zip(specs, curves):
+        U = ksinputs.make_curve(s, c.K + 1)[2]
+        U[:, 0] = U[:, 0].real
+        Us.append(U)
+    opt, prob = _torch_ops_run(_OracleProblem(curves, gap), Us, 6)
+    ops = OracleOps(curves, 0.05)
+    ref = BatchLBFGS(ops, m=4)
+    ref.start(ops.flat(Us))
+    for _ in range(6):
+        ref.iterate(torch.ones(3, dtype=torch.bool))
+    for i in range(3):
+        got, want = prob._get(opt.x, i), ops.unflat(ref.x, i)
+        assert np.abs(got - want).max() <= 1e-10 * np.abs(want).max()
+    assert torch.allclose(opt.J2, ref.J2, rtol=1e-10, atol=0)
