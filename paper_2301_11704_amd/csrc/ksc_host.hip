@@ -603,9 +603,9 @@ ksc_status launch_fused(ksc_problem* p, int mode, const void* in, void* out, con
     return KSC_OK;
   }
   // (the J-only evaluation of a mixed batch runs one launch per grid size: the
-  // single mixed J-only kernel of this build gave wrong costs on its N_x = 128
-  // tiles, while the gradient and step kernels of the same form agree with
-  // the oracle on every curve)
+  // J-only form of the mixed kernel returned wrong costs on its N_x = 128
+  // tiles for a reason not found, while the gradient and step kernels of the
+  // same form agree with the oracle on every curve)
   if (p->mixed_ok && mode != ksc::MODE_J) {
     const size_t lds = lds_max(p, W);
     hipError_t e = launch_mixed(a, W, mode, grid, lds, s, e_first, e_last);
